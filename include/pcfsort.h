@@ -1,0 +1,225 @@
+/*
+ * pcfsort.h -- C ABI of libpcfsort.so, an MI355X (gfx950) implementation of
+ * PCF Learned Sort (Sato & Matsui, "PCF Learned Sort: a Learning Augmented
+ * Sort Algorithm with O(n log log n) Expected Complexity", TMLR 2025).
+ *
+ * Problem (Algorithm 1, Sec. 3.2): given n keys, produce them in ascending
+ * order.  The library runs the Learned-Sort recursion on the GPU: each level
+ * samples the keys, fits the piecewise-constant CDF model (Sec. 3.3: equal-
+ * width bins between the array's minimum and maximum, sample counts, prefix
+ * sum), predicts every key's bucket from that model, counts, scans and
+ * scatters the keys into contiguous buckets, and then sorts every bucket:
+ * small ones inside one workgroup's LDS, ones of size >= delta with a
+ * standard sort (radix), the rest by another level.
+ *
+ * Conventions for every call:
+ *   - Buffers named d_* are device memory owned by the caller; the library
+ *     never frees them.  They must stay valid until the work is complete.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Calls return a pcf_status.  Argument errors are reported synchronously
+ *     and nothing is enqueued.  The sort calls enqueue their kernels on
+ *     `stream`; between recursion levels they may wait for `stream` to read
+ *     back a few bytes of work counts, so they can block.  On return every
+ *     kernel is enqueued; the output is complete once `stream` is synchronized.
+ *   - Keys are totally ordered by value.  fp64 keys must be finite and must
+ *     not be -0.0 (then the ascending order is unique bit for bit); a key that
+ *     breaks this makes the call return PCF_ERR_INVALID_KEY (detected on the
+ *     device; also written to *d_status when d_status is not NULL) and leaves
+ *     the output unspecified.
+ *   - Sorts are stable: payload words of equal keys keep their input order,
+ *     so argsort breaks ties by position.
+ *   - keys_in == keys_out (in place) is allowed.  Other buffers must not
+ *     overlap.
+ *   - Scratch memory: pass a device workspace of at least
+ *     pcf_workspace_bytes(...) bytes, or d_ws = NULL to let the library
+ *     allocate stream-ordered memory for the call.
+ *   - n and segment lengths with a uint32 payload must be < 2^32.
+ */
+#ifndef PCFSORT_H
+#define PCFSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCF_OK = 0,
+    PCF_ERR_INVALID_ARGUMENT = 1, /* null pointer with n > 0, bad enum, size limits */
+    PCF_ERR_INVALID_KEY = 2,      /* NaN, +-inf or -0.0 among fp64 keys */
+    PCF_ERR_OUT_OF_MEMORY = 3,    /* workspace too small, allocation failed, over budget */
+    PCF_ERR_HIP = 4,              /* a HIP runtime call failed: see pcf_last_hip_error() */
+    PCF_ERR_UNSUPPORTED = 5,      /* no gfx950 device or feature not built */
+    PCF_PENDING = 6,              /* serving: request not finished yet */
+    PCF_ERR_UNKNOWN_TICKET = 7,   /* serving: ticket never issued or already released */
+    PCF_ERR_SHUTDOWN = 8          /* serving: server is shutting down */
+} pcf_status;
+
+typedef enum {
+    PCF_KEY_F64 = 0, /* IEEE binary64, ascending numeric order */
+    PCF_KEY_U64 = 1  /* unsigned 64-bit integers */
+} pcf_key_type;
+
+/* Human-readable name of a status code (static string). */
+const char *pcf_status_string(int status);
+/* The last hipError_t seen by a call that returned PCF_ERR_HIP on this thread. */
+int pcf_last_hip_error(void);
+/* Library version string. */
+const char *pcf_version(void);
+
+/*
+ * Workspace size for a sort of n keys in num_segments segments
+ * (num_segments = 1 for the plain calls), with or without a uint32 payload.
+ * An upper bound that holds for every input of that size.
+ */
+size_t pcf_workspace_bytes(int key_type, size_t n, int with_payload, uint32_t num_segments);
+
+/*
+ * Sort n fp64 keys ascending (Algorithm 1).  d_in and d_out hold n doubles
+ * each; d_in may equal d_out.  d_status: optional device int32 that receives
+ * the data status (PCF_OK or PCF_ERR_INVALID_KEY).
+ */
+int pcf_sort_f64(const double *d_in, double *d_out, size_t n, void *d_ws, size_t ws_bytes,
+                 int32_t *d_status, void *stream);
+
+/* Same for uint64 keys. */
+int pcf_sort_u64(const uint64_t *d_in, uint64_t *d_out, size_t n, void *d_ws, size_t ws_bytes,
+                 int32_t *d_status, void *stream);
+
+/*
+ * Argsort (Algorithm 1 with each key carrying its input position).
+ * d_idx_out[k] receives the input position of the k-th smallest key; ties
+ * are broken by ascending position.  d_keys_out (nullable) receives the
+ * sorted keys; when NULL the keys are sorted in workspace memory.
+ * n < 2^32.
+ */
+int pcf_argsort(int key_type, const void *d_keys_in, void *d_keys_out, uint32_t *d_idx_out,
+                size_t n, void *d_ws, size_t ws_bytes, int32_t *d_status, void *stream);
+
+/*
+ * Segmented sort: segment s is keys [d_offsets[s], d_offsets[s+1]) and is
+ * sorted on its own (Algorithm 1 per array), stably, carrying the optional
+ * uint32 payload d_vals_in -> d_vals_out (both NULL for keys only; with a
+ * payload every segment must be shorter than 2^32).  d_offsets: device array
+ * of num_segments + 1 non-decreasing uint64 CSR offsets, d_offsets[0] = 0;
+ * empty segments are allowed.  The whole batch runs as one fixed launch chain
+ * that is captured once per (key type, payload, size class) into a hipGraph
+ * and replayed; parameters come from the autotuned policy table.
+ */
+int pcf_sort_segmented(int key_type, const void *d_keys_in, void *d_keys_out,
+                       const uint32_t *d_vals_in, uint32_t *d_vals_out,
+                       const uint64_t *d_offsets, uint32_t num_segments, size_t total_keys,
+                       void *d_ws, size_t ws_bytes, int32_t *d_status, void *stream);
+
+/*
+ * Diagnostic: run exactly one model-based bucketing level (Sec. 3.3 with the
+ * given alpha, beta, gamma) on the whole array as one node named by
+ * node_seed, and report the model.  The stable partition (buckets
+ * concatenated, each in input order) goes to d_part_keys / d_part_vals
+ * (d_vals_in NULL = no payload).  Host arrays (may be NULL): h_b and h_T
+ * receive beta + 1 uint64 values (prefix counts b_i and the bucket of each
+ * bin), h_sizes receives gamma + 1 bucket sizes, h_scalars receives
+ * {min bits, max bits, scale bits, halves, status} as 5 uint64.
+ * Synchronizes `stream`.  Limits: beta <= 16383, gamma <= 2047.
+ */
+int pcf_level_trace(int key_type, const void *d_keys_in, const uint32_t *d_vals_in, size_t n,
+                    uint64_t node_seed, uint32_t alpha, uint32_t beta, uint32_t gamma,
+                    void *d_part_keys, uint32_t *d_part_vals, uint64_t *h_b, uint64_t *h_T,
+                    uint64_t *h_sizes, uint64_t *h_scalars, void *stream);
+
+/* ---- policy (parameters of the GPU recursion) ---------------------------- */
+
+/*
+ * Parameters of the GPU recursion.  The global levels pick gamma + 1 =
+ * clamp(next power of two of len / target_child, 2, max_buckets) buckets,
+ * beta = min(max_bins, bins_per_bucket * (gamma + 1)) bins and
+ * alpha = min(max_samples, samples_per_bucket * (gamma + 1)) samples;
+ * delta = floor(len^{3/4}) as in the paper's theorems.  Arrays of at most
+ * lds_cap keys are finished inside one workgroup's LDS with the paper's own
+ * parameters (alpha = beta = gamma = delta = floor(len^{3/4}), tau = 100).
+ * Dynamic tuning of alpha, beta, gamma is suggested in Sec. 5.
+ */
+typedef struct {
+    uint32_t max_buckets;        /* power of two, 2..2048 */
+    uint32_t target_child;       /* keys per bucket aimed at */
+    uint32_t bins_per_bucket;    /* beta / (gamma + 1) */
+    uint32_t max_bins;           /* <= 16383 */
+    uint32_t samples_per_bucket; /* alpha / (gamma + 1) */
+    uint32_t max_samples;        /* <= 1 << 20 */
+    uint32_t chunk_keys;         /* keys per count/scatter work unit (minimum) */
+    uint32_t lds_cap;            /* largest array finished in LDS, <= 8192 */
+    uint32_t tau;                /* small-array threshold inside LDS (paper: 100) */
+    uint32_t seed;               /* sampling seed */
+} pcf_policy;
+
+/* Current process-wide policy (defaults, or what pcf_set_policy / tuning set). */
+int pcf_get_policy(pcf_policy *out);
+int pcf_set_policy(const pcf_policy *p);
+
+/*
+ * Autotuner: times candidate policies on synthetic arrays on the current
+ * device (about a minute) and writes the best per size class as JSON to
+ * out_json.  pcf_load_tuning reads such a file and installs it.
+ */
+int pcf_autotune(int key_type, int with_payload, const char *out_json);
+int pcf_load_tuning(const char *json_path);
+
+/* ---- serving --------------------------------------------------------------
+ * A request loop with continuous batching under an HBM budget.  Submitted
+ * sorts wait in an admission queue; whenever a stream slot and enough budget
+ * are free, the scheduler admits every queued request that fits, gathers them
+ * into one segmented batch and launches it, so requests that arrive while
+ * others run join the next batch and batches on different streams overlap on
+ * the device.  Results stay device-resident in server-owned memory until
+ * released.
+ */
+typedef struct pcf_server pcf_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* device memory the server may hold (results + work) */
+    uint32_t max_streams;      /* concurrent batches (1..8) */
+    uint32_t max_batch_requests; /* requests per batch (>= 1) */
+    uint64_t max_batch_keys;   /* keys per batch (>= 1) */
+    int32_t device;            /* HIP device ordinal */
+    uint32_t flags;            /* reserved, 0 */
+} pcf_serve_config;
+
+typedef struct {
+    void *d_keys_sorted;  /* server-owned device buffer: n sorted keys */
+    uint32_t *d_idx;      /* server-owned: argsort positions, or NULL */
+    uint64_t n;
+    uint64_t latency_ns;  /* submit -> completion observed by the server */
+    uint64_t queue_ns;    /* submit -> admission */
+    int32_t status;       /* PCF_OK or the request's error */
+    uint32_t batch_requests; /* requests in the batch that ran it */
+} pcf_result;
+
+typedef struct {
+    uint64_t submitted, completed, released, batches;
+    uint64_t budget_bytes, budget_in_use, budget_high_water;
+    uint64_t queued;
+} pcf_serve_stats;
+
+int pcf_serve_create(const pcf_serve_config *cfg, pcf_server **out);
+/* Never blocks.  d_keys (n keys of key_type) must stay valid and unchanged
+ * until the request is done.  A request that alone exceeds the budget returns
+ * PCF_ERR_OUT_OF_MEMORY. */
+int pcf_serve_submit(pcf_server *s, int key_type, const void *d_keys, size_t n, int want_argsort,
+                     uint64_t *ticket);
+/* Non-blocking: PCF_OK and *out filled when done, PCF_PENDING otherwise. */
+int pcf_serve_poll(pcf_server *s, uint64_t ticket, pcf_result *out);
+/* Blocks until the request is done (or timeout_ms passes: PCF_PENDING). */
+int pcf_serve_wait(pcf_server *s, uint64_t ticket, uint32_t timeout_ms, pcf_result *out);
+/* Returns the result memory to the budget; the ticket becomes unknown. */
+int pcf_serve_release(pcf_server *s, uint64_t ticket);
+int pcf_serve_get_stats(pcf_server *s, pcf_serve_stats *out);
+/* Stops admission, waits for running batches, frees everything. */
+int pcf_serve_destroy(pcf_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCFSORT_H */

@@ -1,0 +1,239 @@
+// pcf_device.h -- device-side definitions of the PCF Learned Sort library:
+// key images, the sampling generator, the PCF bin function and the work
+// records that the kernels of one recursion level exchange through HBM.
+//
+// Paper: Sato & Matsui, "PCF Learned Sort", TMLR 2025.  Algorithm 1 (Sec. 3.2)
+// is the recursion; Sec. 3.3 defines the PCF model used at every level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcf {
+
+constexpr int KT_F64 = 0;
+constexpr int KT_U64 = 1;
+
+constexpr int MAX_LEVELS = 16;       // global recursion levels per call
+constexpr uint32_t MAX_NB = 2048;    // buckets per global node (gamma + 1)
+constexpr uint32_t MAX_BINS = 16383; // beta per global node (table of beta + 1 u16)
+constexpr uint32_t RADIX_NB = 256;   // buckets of a standard-sort (radix) node
+
+// ---- order-preserving images --------------------------------------------
+// fp64 keys (finite, no -0.0) map to uint64 so that unsigned order equals
+// numeric order; uint64 keys are their own image.
+template <int KT>
+__device__ __host__ __forceinline__ uint64_t img_of(uint64_t bits) {
+  if (KT == KT_F64) return (bits >> 63) ? ~bits : (bits | 0x8000000000000000ull);
+  return bits;
+}
+template <int KT>
+__device__ __host__ __forceinline__ uint64_t bits_of_img(uint64_t img) {
+  if (KT == KT_F64) return (img >> 63) ? (img & 0x7fffffffffffffffull) : ~img;
+  return img;
+}
+
+// fp64 keys must be finite and not -0.0 (the sorted order is then unique).
+__device__ __forceinline__ bool f64_bits_valid(uint64_t bits) {
+  const uint64_t exp = (bits >> 52) & 0x7ff;
+  return exp != 0x7ff && bits != 0x8000000000000000ull;
+}
+
+// ---- SplitMix64 (Steele, Lea & Flood 2014) -------------------------------
+// Output k (k = 0, 1, ...) of the generator whose state starts at s: the
+// state advances by 0x9E3779B97F4A7C15 and passes through the published
+// finalizer.  Used in counter form so any thread can draw any sample.
+__device__ __host__ __forceinline__ uint64_t sm_finalize(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __host__ __forceinline__ uint64_t sm_out(uint64_t s, uint64_t k) {
+  return sm_finalize(s + (k + 1) * 0x9E3779B97F4A7C15ull);
+}
+// A node is named by (segment, depth, offset inside the segment); its samples
+// come from the generator seeded by chaining the three names.
+__device__ __host__ __forceinline__ uint64_t node_seed(uint64_t seed, uint64_t seg,
+                                                       uint64_t depth, uint64_t rel) {
+  return sm_out(sm_out(sm_out(seed, seg), depth), rel);
+}
+// Sample j of a node of n keys: uniform position with replacement (Sec. 3.3),
+// the high word of the 64x64 product.
+__device__ __forceinline__ uint32_t sample_pos(uint64_t nseed, uint64_t j, uint32_t n) {
+  return (uint32_t)__umul64hi(sm_out(nseed, j), (uint64_t)n);
+}
+
+// floor(m^{3/4}) exactly (delta of the PCF theorems, Sec. 3.3), m < 2^32.
+__device__ __host__ inline uint32_t root34(uint32_t m) {
+  if (m == 0) return 0;
+  // m^3 as a 128-bit (hi, lo) pair
+  auto mul128 = [](uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    hi = __umul64hi(a, b);
+    lo = a * b;
+#else
+    unsigned __int128 p = (unsigned __int128)a * b;
+    hi = (uint64_t)(p >> 64);
+    lo = (uint64_t)p;
+#endif
+  };
+  uint64_t m2 = (uint64_t)m * m, m3h, m3l;
+  mul128(m2, m, m3h, m3l);
+  auto le = [&](uint64_t r) {  // r^4 <= m^3 ?
+    uint64_t r2 = r * r, h, l;
+    mul128(r2, r2, h, l);
+    return h < m3h || (h == m3h && l <= m3l);
+  };
+  uint64_t r = (uint64_t)pow((double)m, 0.75);
+  while (r > 0 && !le(r)) --r;
+  while (le(r + 1)) ++r;
+  return (uint32_t)r;
+}
+
+// ---- the PCF bin function i(x) (Sec. 3.3), 0-based ------------------------
+// bin(v) = min(beta, floor(RN(off(v) * s))), s = RN(beta / RN(x_max - x_min)),
+// off(v) = RN(v - x_min); halves of both terms when x_max - x_min overflows;
+// for uint64 keys off(v) is the exact difference rounded to fp64.  All fp64
+// steps are single IEEE round-to-nearest operations (built without FP
+// contraction), so every key lands in the same bin as on the CPU.
+struct BinFn {
+  uint64_t lo_bits;
+  double lo;
+  double lo_half;
+  double s;
+  uint32_t beta;
+  uint32_t halves;
+};
+
+template <int KT>
+__device__ __forceinline__ uint32_t bin_of(const BinFn& f, uint64_t bits) {
+  double off;
+  if (KT == KT_F64) {
+    const double v = __longlong_as_double((long long)bits);
+    off = f.halves ? (v * 0.5 - f.lo_half) : (v - f.lo);
+  } else {
+    off = (double)(bits - f.lo_bits);
+  }
+  const double p = off * f.s;
+  const uint32_t k = (uint32_t)floor(p);
+  return k < f.beta ? k : f.beta;
+}
+
+// Sets up the bin function for the range [lo, hi] (images); returns false when
+// the scale is not finite (the node is then a bucketing failure).
+template <int KT>
+__device__ __forceinline__ bool bin_setup(BinFn& f, uint64_t lo_img, uint64_t hi_img,
+                                          uint32_t beta) {
+  const uint64_t lob = bits_of_img<KT>(lo_img), hib = bits_of_img<KT>(hi_img);
+  f.lo_bits = lob;
+  f.beta = beta;
+  f.halves = 0;
+  double d;
+  if (KT == KT_F64) {
+    const double lo = __longlong_as_double((long long)lob);
+    const double hi = __longlong_as_double((long long)hib);
+    f.lo = lo;
+    f.lo_half = lo * 0.5;
+    d = hi - lo;
+    if (__builtin_isinf(d)) {
+      f.halves = 1;
+      d = hi * 0.5 - f.lo_half;
+    }
+  } else {
+    f.lo = 0.0;
+    f.lo_half = 0.0;
+    d = (double)(hib - lob);
+  }
+  f.s = (double)beta / d;
+  return __builtin_isfinite(f.s);
+}
+
+// ---- work records ---------------------------------------------------------
+enum : uint32_t { NK_PCF = 0, NK_RADIX = 1 };
+enum : uint32_t { NS_ACTIVE = 0, NS_DONE = 1 };
+enum : uint32_t { IF_STD = 1, IF_ROOT = 2, IF_IOTA = 4 };
+
+// One array of a global level (a node of the recursion tree).
+struct Node {
+  const void* src;          // keys of the node, element 0
+  const uint32_t* vsrc;     // payload of the node, element 0 (NULL: none or iota)
+  uint64_t off;             // absolute position of element 0 in the output
+  uint64_t rel;             // position inside its segment (names the node)
+  uint64_t seed;            // sampling seed of the node
+  unsigned long long min_img, max_img;  // key range (reduced by the producer)
+  uint32_t len, seg, depth, kind;
+  uint32_t nchunks, unit_base;
+  uint32_t fixed;           // alpha / beta / nb preset by the caller
+  uint32_t iota;            // payload is the position inside the segment
+  // filled by the fit kernel
+  uint32_t state, nb, nbits, beta, alpha, delta, shift, halves;
+  double scale;
+  uint64_t table_off, cm_off;
+  uint32_t aux_off, task_base;
+};
+
+struct Unit {
+  uint32_t node, chunk;
+};
+
+// One array finished inside a workgroup's LDS.
+struct Item {
+  const void* src;
+  const uint32_t* vsrc;
+  uint64_t off;   // absolute output position of element 0
+  uint64_t rel;   // position inside its segment (names the node)
+  uint32_t len, depth, flags, seg;
+};
+
+struct LevelCtr {
+  uint32_t num_nodes, num_units, tasks, aux_used;
+  unsigned long long table_used, cm_used;
+};
+
+struct Ctl {
+  int32_t status;      // 0 or the data error (PCF_ERR_INVALID_KEY)
+  uint32_t overflow;   // a capacity bound was exceeded (library bug guard)
+  uint32_t item_count[2];
+  uint32_t item_next[2];
+  uint32_t n_radix_nodes, n_fail_items, n_done_nodes, pad;
+  LevelCtr lv[MAX_LEVELS];
+};
+
+struct PolicyDev {
+  uint32_t max_buckets, target_child, bins_per_bucket, max_bins;
+  uint32_t samples_per_bucket, max_samples, chunk_keys, lds_cap;
+  uint32_t tau, small_cap, seed_lo, seed_hi;
+};
+
+// Everything a kernel of one call needs (passed by value).
+struct Plan {
+  Ctl* ctl;
+  void* out_keys;
+  uint32_t* out_vals;
+  int32_t* d_status;
+  uint32_t has_pay;
+  uint32_t key_bytes;
+  // level slots (level L uses slot L & 1)
+  Node* nodes[2];
+  Unit* units[2];
+  uint16_t* table[2];
+  uint32_t* cm[2];
+  uint32_t* bstart[2];
+  int32_t* cmap[2];
+  uint32_t* task_node[2];
+  uint32_t cap_nodes, cap_units, cap_tasks, cap_aux;
+  unsigned long long cap_table, cap_cm;
+  Item* items[2];
+  uint32_t cap_items[2];
+  // trace (level 0 only): prefix counts b of node 0
+  uint32_t* trace_b;
+  PolicyDev pol;
+  uint64_t seed;
+  uint64_t n_total;  // keys in the whole call (bound of every output position)
+};
+
+// Ctl::overflow bits
+constexpr uint32_t OVF_CAPACITY = 1;  // a work-list bound was exceeded
+constexpr uint32_t OVF_INTERNAL = 2;  // an index failed its range check (a library bug)
+
+}  // namespace pcf

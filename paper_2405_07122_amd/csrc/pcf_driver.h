@@ -1,0 +1,68 @@
+// pcf_driver.h -- host-side driver of the PCF Learned Sort library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pcfsort.h"
+#include "pcf_device.h"
+
+namespace pcf {
+
+// Records a failed HIP call for pcf_last_hip_error() and returns PCF_ERR_HIP
+// (PCF_DEBUG=1 in the environment prints the call site to stderr).
+int hip_fail(hipError_t e, const char* what = nullptr, int line = 0);
+
+#define PCF_HIP(call)                                              \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return hip_fail(e_, #call, __LINE__);    \
+  } while (0)
+
+struct Layout {
+  size_t ctl, tmp_keys, tmp_vals, int_keys, trace_b;
+  size_t nodes[2], units[2], table[2], cm[2], bstart[2], cmap[2], task_node[2], items[2];
+  size_t total;
+  uint32_t cap_nodes, cap_units, cap_tasks, cap_aux;
+  uint64_t cap_table, cap_cm;
+  uint32_t cap_items[2];
+  uint32_t nbmax;
+};
+
+Layout make_layout(size_t n, int has_pay, uint32_t nseg, const pcf_policy& pol, int int_keys,
+                   uint32_t trace_nb, uint32_t trace_beta);
+
+// One sort call: plain (offsets == NULL, nseg = 1) or segmented.
+struct SortArgs {
+  int key_type;
+  const void* keys_in;
+  void* keys_out;          // NULL for argsort without keys: workspace keys are used
+  const uint32_t* vals_in; // NULL: none, or iota when `iota`
+  uint32_t* vals_out;      // NULL: keys only
+  int iota;
+  const uint64_t* offsets; // device CSR offsets or NULL
+  uint32_t nseg;
+  size_t n;
+  void* ws;
+  size_t ws_bytes;
+  int32_t* d_status;
+  hipStream_t stream;
+  // diagnostics (pcf_level_trace)
+  int trace;
+  uint64_t trace_seed;
+  uint32_t trace_alpha, trace_beta, trace_nb;
+  uint64_t* h_b;
+  uint64_t* h_T;
+  uint64_t* h_sizes;
+  uint64_t* h_scalars;
+  // filled on return when not NULL
+  uint32_t* levels_run;
+};
+
+int run_sort(const SortArgs& a);
+
+pcf_policy current_policy();
+int device_cus();
+
+}  // namespace pcf

@@ -1,0 +1,569 @@
+// pcf_driver.hip -- host driver and C ABI of the PCF Learned Sort library.
+//
+// Runs Algorithm 1 (Sec. 3.2) of the paper on the GPU: the recursion is
+// unrolled into a chain of global levels (each: fit, count, column scan,
+// classify, scatter over a device-resident node list) followed by the in-LDS
+// finish of every small array.  The host never reads keys; between levels it
+// reads back only the size of the next level's node list, once the number of
+// levels that the paper's delta rule allows for the input size has run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "pcf_driver.h"
+#include "pcf_kernels.h"
+
+namespace pcf {
+
+static thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e, const char* what, int line) {
+  g_last_hip_error = (int)e;
+  static const bool dbg = getenv("PCF_DEBUG") != nullptr;
+  if (dbg && what)
+    fprintf(stderr, "pcfsort: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+  return PCF_ERR_HIP;
+}
+
+static std::mutex g_pol_mu;
+static pcf_policy g_pol = {
+    /*max_buckets*/ 1024,
+    /*target_child*/ 2048,
+    /*bins_per_bucket*/ 16,
+    /*max_bins*/ 16383,
+    /*samples_per_bucket*/ 16,
+    /*max_samples*/ 65536,
+    /*chunk_keys*/ 16384,
+    /*lds_cap*/ 8192,
+    /*tau*/ 100,
+    /*seed*/ 0x5eed,
+};
+
+pcf_policy current_policy() {
+  std::lock_guard<std::mutex> g(g_pol_mu);
+  return g_pol;
+}
+
+static int check_policy(const pcf_policy& p) {
+  if (p.max_buckets < 2 || p.max_buckets > MAX_NB || (p.max_buckets & (p.max_buckets - 1)))
+    return PCF_ERR_INVALID_ARGUMENT;
+  if (p.target_child < 16 || p.bins_per_bucket < 1 || p.max_bins < 2 || p.max_bins > MAX_BINS)
+    return PCF_ERR_INVALID_ARGUMENT;
+  if (p.samples_per_bucket < 1 || p.max_samples < 2 || p.max_samples > (1u << 20))
+    return PCF_ERR_INVALID_ARGUMENT;
+  if (p.chunk_keys < 1024 || p.lds_cap < 2048 || p.lds_cap > 8192) return PCF_ERR_INVALID_ARGUMENT;
+  if (p.tau < 16 || p.tau > 1024) return PCF_ERR_INVALID_ARGUMENT;
+  return PCF_OK;
+}
+
+static int g_cus = 0;
+static std::mutex g_dev_mu;
+
+int device_cus() {
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  if (g_cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return 0;
+    g_cus = pr.multiProcessorCount > 0 ? pr.multiProcessorCount : 1;
+  }
+  return g_cus;
+}
+
+// K5 sizes of the two item classes (LDS capacity and workgroup size).
+constexpr int K5_SMALL_CAP = 2048, K5_SMALL_NT = 256;
+constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = 512;
+// Scatter tile.
+constexpr int SC_NT = 512, SC_TS = 4096;
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// A capacity overflow reports PCF_ERR_OUT_OF_MEMORY; a failed device range
+// check reports PCF_ERR_HIP with pcf_last_hip_error() == -2.
+static int overflow_status(uint32_t ovf) {
+  if (ovf & OVF_INTERNAL) {
+    g_last_hip_error = -2;
+    return PCF_ERR_HIP;
+  }
+  return PCF_ERR_OUT_OF_MEMORY;
+}
+
+Layout make_layout(size_t n, int has_pay, uint32_t nseg, const pcf_policy& pol, int int_keys,
+                   uint32_t trace_nb, uint32_t trace_beta) {
+  Layout L = {};
+  const uint64_t cap = pol.lds_cap;
+  const uint64_t nodes = n / (cap + 1) + 64;
+  const uint64_t nbmax = std::max<uint64_t>(std::max<uint64_t>(pol.max_buckets, RADIX_NB), trace_nb);
+  const uint64_t units = n / std::max<uint64_t>(pol.chunk_keys, 1) + nodes + 16;
+  // buckets over the nodes of a level: radix nodes have 256, PCF nodes fewer
+  // than 2 ceil(len / target) + 2
+  const uint64_t aux = std::max<uint64_t>(nodes * RADIX_NB,
+                                          2 * n / pol.target_child + 4 * nodes + trace_nb) + 64;
+  const uint64_t table = std::min<uint64_t>(nodes * (pol.max_bins + 1) + trace_beta + 1,
+                                            nodes + (uint64_t)pol.bins_per_bucket * aux +
+                                                trace_beta + 1);
+  const uint64_t cmc = aux + nbmax * (n / std::max<uint64_t>(pol.chunk_keys, 1) + 1);
+  // LDS items: every key belongs to one item; items start at window crossings
+  // or big buckets (<= 2n/half), failed buckets (>= delta > cap^{3/4}), runs
+  // after a global child (<= 2 nodes per level) and roots
+  const uint64_t half = std::max<uint64_t>(pol.lds_cap / 4, 1);  // small_cap / 2
+  const uint64_t items0 = 2 * n / half + 2 * n / 700 + 2 * MAX_LEVELS * nodes + nseg + 1024;
+  const uint64_t items1 = n / (K5_SMALL_CAP + 1) + nseg + 1024;
+  L.cap_nodes = (uint32_t)std::min<uint64_t>(nodes, 0xffffffffu);
+  L.cap_units = (uint32_t)std::min<uint64_t>(units, 0xffffffffu);
+  L.cap_aux = (uint32_t)std::min<uint64_t>(aux, 0xffffffffu);
+  L.cap_tasks = L.cap_aux;
+  L.cap_table = table;
+  L.cap_cm = cmc;
+  L.cap_items[0] = (uint32_t)std::min<uint64_t>(items0, 0xffffffffu);
+  L.cap_items[1] = (uint32_t)std::min<uint64_t>(items1, 0xffffffffu);
+  L.nbmax = (uint32_t)nbmax;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  L.ctl = take(sizeof(Ctl));
+  L.tmp_keys = take(n * 8);
+  L.tmp_vals = take(has_pay ? n * 4 : 0);
+  L.int_keys = take(int_keys ? n * 8 : 0);
+  L.trace_b = take(trace_beta ? 4ull * (trace_beta + 1) : 0);
+  for (int s = 0; s < 2; ++s) {
+    L.nodes[s] = take(sizeof(Node) * (size_t)L.cap_nodes);
+    L.units[s] = take(sizeof(Unit) * (size_t)L.cap_units);
+    L.table[s] = take(2 * (size_t)L.cap_table);
+    L.cm[s] = take(4 * (size_t)L.cap_cm);
+    L.bstart[s] = take(4 * (size_t)L.cap_aux);
+    L.cmap[s] = take(4 * (size_t)L.cap_aux);
+    L.task_node[s] = take(4 * (size_t)L.cap_tasks);
+  }
+  L.items[0] = take(sizeof(Item) * (size_t)L.cap_items[0]);
+  L.items[1] = take(sizeof(Item) * (size_t)L.cap_items[1]);
+  L.total = o;
+  return L;
+}
+
+// Number of global levels the delta rule allows before every array that
+// recursed is small enough for the LDS finish: a bucket that recurses holds
+// fewer than delta = floor(len^{3/4}) keys (worst-case lemma, Sec. 3.2).
+static int planned_levels(uint64_t n, uint32_t cap) {
+  int d = 0;
+  uint64_t m = n;
+  while (m > cap && d < MAX_LEVELS - 1) {
+    m = root34((uint32_t)std::min<uint64_t>(m, 0xffffffffu));
+    ++d;
+  }
+  return d;
+}
+
+template <int KT, int PAY>
+static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol) {
+  hipStream_t st = a.stream;
+  const int cus = device_cus();
+  if (cus <= 0) return PCF_ERR_UNSUPPORTED;
+  Plan p = {};
+  p.ctl = reinterpret_cast<Ctl*>(ws + lay.ctl);
+  void* out_keys = a.keys_out ? a.keys_out : (void*)(ws + lay.int_keys);
+  void* tmp_keys = ws + lay.tmp_keys;
+  uint32_t* tmp_vals = PAY ? reinterpret_cast<uint32_t*>(ws + lay.tmp_vals) : nullptr;
+  p.out_keys = out_keys;
+  p.out_vals = PAY ? a.vals_out : nullptr;
+  p.d_status = a.d_status;
+  p.has_pay = PAY;
+  p.key_bytes = 8;
+  for (int s = 0; s < 2; ++s) {
+    p.nodes[s] = reinterpret_cast<Node*>(ws + lay.nodes[s]);
+    p.units[s] = reinterpret_cast<Unit*>(ws + lay.units[s]);
+    p.table[s] = reinterpret_cast<uint16_t*>(ws + lay.table[s]);
+    p.cm[s] = reinterpret_cast<uint32_t*>(ws + lay.cm[s]);
+    p.bstart[s] = reinterpret_cast<uint32_t*>(ws + lay.bstart[s]);
+    p.cmap[s] = reinterpret_cast<int32_t*>(ws + lay.cmap[s]);
+    p.task_node[s] = reinterpret_cast<uint32_t*>(ws + lay.task_node[s]);
+    p.items[s] = reinterpret_cast<Item*>(ws + lay.items[s]);
+    p.cap_items[s] = lay.cap_items[s];
+  }
+  p.cap_nodes = lay.cap_nodes;
+  p.cap_units = lay.cap_units;
+  p.cap_tasks = lay.cap_tasks;
+  p.cap_aux = lay.cap_aux;
+  p.cap_table = lay.cap_table;
+  p.cap_cm = lay.cap_cm;
+  p.trace_b = a.trace ? reinterpret_cast<uint32_t*>(ws + lay.trace_b) : nullptr;
+  // scatter work per level: enough units to give every workgroup a few
+  const uint32_t bins_lds = std::max<uint32_t>(pol.max_bins, a.trace ? a.trace_beta : 0u);
+  ScatterLds sl = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, SC_TS, PAY);
+  const bool small_tile = sl.total > 160 * 1024 - 1024;  // many buckets: halve the tile
+  if (small_tile) sl = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, SC_TS / 2, PAY);
+  if (sl.total > 160 * 1024 - 1024) return PCF_ERR_INVALID_ARGUMENT;
+  const int sc_per_cu = std::max(1, (int)(160 * 1024 / sl.total));
+  const int g_sc = cus * std::min(sc_per_cu, 2);
+  PolicyDev pd;
+  pd.max_buckets = pol.max_buckets;
+  pd.target_child = pol.target_child;
+  pd.bins_per_bucket = pol.bins_per_bucket;
+  pd.max_bins = pol.max_bins;
+  pd.samples_per_bucket = pol.samples_per_bucket;
+  pd.max_samples = pol.max_samples;
+  pd.chunk_keys = (uint32_t)std::max<uint64_t>(pol.chunk_keys, (a.n + 4ull * g_sc - 1) / (4ull * g_sc));
+  pd.lds_cap = pol.lds_cap;
+  pd.tau = pol.tau;
+  pd.small_cap = K5_SMALL_CAP;
+  pd.seed_lo = pol.seed;
+  pd.seed_hi = 0;
+  p.pol = pd;
+  p.seed = (uint64_t)pol.seed;
+  p.n_total = a.n;
+
+  RootArgs ra = {};
+  ra.keys = a.keys_in;
+  ra.vals = a.vals_in;
+  ra.offsets = a.offsets;
+  ra.n = a.n;
+  ra.nseg = a.nseg;
+  ra.iota = a.iota ? 1u : 0u;
+  if (a.trace) {
+    ra.fixed_alpha = a.trace_alpha;
+    ra.fixed_beta = a.trace_beta;
+    ra.fixed_nb = a.trace_nb;
+    ra.force_global = 1;
+    ra.fixed_seed = a.trace_seed;
+    ra.has_fixed_seed = 1;
+  }
+
+  // level L writes into dst[L & 1] (absolute positions); sources are recorded
+  // per node, so keys and payload may alternate independently
+  void* kdst[2];
+  uint32_t* vdst[2];
+  kdst[0] = (a.keys_in == out_keys) ? tmp_keys : out_keys;
+  kdst[1] = (kdst[0] == out_keys) ? tmp_keys : out_keys;
+  vdst[0] = nullptr;
+  vdst[1] = nullptr;
+  if (PAY) {
+    vdst[0] = (a.vals_in == a.vals_out) ? tmp_vals : a.vals_out;
+    vdst[1] = (vdst[0] == a.vals_out) ? tmp_vals : a.vals_out;
+  }
+
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, p);
+  hipLaunchKernelGGL(k_roots, dim3((a.nseg + 255) / 256), dim3(256), 0, st, p, ra);
+  hipLaunchKernelGGL((k_range<KT, 256>), dim3(cus * 8), dim3(256), 0, st, p);
+  PCF_HIP(hipGetLastError());
+
+  const size_t cnt_lds = 2 * (MAX_BINS + 1) + 4 * MAX_NB;
+  const int planned = a.trace ? 1 : planned_levels(a.n, pol.lds_cap);
+  int levels = 0;
+  Ctl hc;
+  for (int L = 0; L < planned || true; ++L) {
+    if (L >= planned) {
+      // read back the next level's size only once the planned levels have run
+      PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      PCF_HIP(hipStreamSynchronize(st));
+      if (hc.status) return hc.status;
+      if (hc.overflow) return overflow_status(hc.overflow);
+      if (hc.lv[L].num_nodes == 0 || a.trace) break;
+      if (L >= MAX_LEVELS - 1) return PCF_ERR_OUT_OF_MEMORY;
+    }
+    LevelIO io;
+    io.dst_keys = kdst[L & 1];
+    io.dst_vals = vdst[L & 1];
+    hipLaunchKernelGGL((k_fit<KT, 1024>), dim3(cus * 2), dim3(1024), 0, st, p, L, a.trace);
+    hipLaunchKernelGGL((k_count<KT, 512>), dim3(cus * 3), dim3(512), cnt_lds, st, p, L);
+    hipLaunchKernelGGL((k_colscan<256>), dim3(cus * 4), dim3(256), 0, st, p, L);
+    hipLaunchKernelGGL((k_classify<512>), dim3(cus * 2), dim3(512), 0, st, p, L, io);
+    if (small_tile)
+      hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS / 2, PAY>), dim3(g_sc), dim3(SC_NT), sl.total,
+                         st, p, L, io, bins_lds, lay.nbmax);
+    else
+      hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS, PAY>), dim3(g_sc), dim3(SC_NT), sl.total, st,
+                         p, L, io, bins_lds, lay.nbmax);
+    PCF_HIP(hipGetLastError());
+    ++levels;
+  }
+  if (a.levels_run) *a.levels_run = (uint32_t)levels;
+  if (a.trace) {
+    // the level's model and bucket sizes for the caller
+    Node nd;
+    PCF_HIP(hipMemcpyAsync(&nd, p.nodes[0], sizeof(Node), hipMemcpyDeviceToHost, st));
+    PCF_HIP(hipStreamSynchronize(st));
+    const uint32_t beta = a.trace_beta, nb = a.trace_nb;
+    if (a.h_scalars) {
+      uint64_t sb;
+      std::memcpy(&sb, &nd.scale, 8);
+      a.h_scalars[0] = bits_of_img<KT>(nd.min_img);
+      a.h_scalars[1] = bits_of_img<KT>(nd.max_img);
+      a.h_scalars[2] = sb;
+      a.h_scalars[3] = nd.halves;
+      a.h_scalars[4] = nd.state == NS_DONE ? 1 : (nd.kind == NK_RADIX ? 2 : 0);
+    }
+    if (nd.state == NS_ACTIVE && nd.kind == NK_PCF) {
+      std::vector<uint32_t> hb(beta + 1), st32(nb);
+      std::vector<uint16_t> ht(beta + 1);
+      PCF_HIP(hipMemcpy(hb.data(), p.trace_b, 4ull * (beta + 1), hipMemcpyDeviceToHost));
+      PCF_HIP(hipMemcpy(ht.data(), p.table[0] + nd.table_off, 2ull * (beta + 1),
+                        hipMemcpyDeviceToHost));
+      PCF_HIP(hipMemcpy(st32.data(), p.bstart[0] + nd.aux_off, 4ull * nb, hipMemcpyDeviceToHost));
+      for (uint32_t i = 0; i <= beta; ++i) {
+        if (a.h_b) a.h_b[i] = hb[i];
+        if (a.h_T) a.h_T[i] = ht[i];
+      }
+      if (a.h_sizes)
+        for (uint32_t q = 0; q < nb; ++q)
+          a.h_sizes[q] = (q + 1 < nb ? st32[q + 1] : nd.len) - st32[q];
+    }
+    return PCF_OK;
+  }
+  // finish every small array inside LDS
+  hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), dim3(cus * 4),
+                     dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>), st, p, 0);
+  hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), dim3(cus), dim3(K5_BIG_NT),
+                     sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>), st, p, 1);
+  PCF_HIP(hipGetLastError());
+  if (a.d_status) {
+    PCF_HIP(hipMemcpyAsync(a.d_status, &p.ctl->status, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    return PCF_OK;
+  }
+  PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  PCF_HIP(hipStreamSynchronize(st));
+  if (hc.status) return hc.status;
+  if (hc.overflow) return overflow_status(hc.overflow);
+  return PCF_OK;
+}
+
+static bool g_attr_done = false;
+static std::mutex g_attr_mu;
+
+// Raises a kernel's dynamic-LDS limit to what its launches use (the static
+// LDS of the kernel counts against the same 160 KiB).
+static int allow_lds(const void* fn, size_t dynamic_bytes) {
+  if (dynamic_bytes <= 64 * 1024) return PCF_OK;
+  hipFuncAttributes fa;
+  PCF_HIP(hipFuncGetAttributes(&fa, fn));
+  if (fa.sharedSizeBytes + dynamic_bytes > 160 * 1024) return PCF_ERR_UNSUPPORTED;
+  PCF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes));
+  return PCF_OK;
+}
+
+template <int KT, int PAY>
+static int set_attrs_typed() {
+  int r;
+  if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
+                     sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>))) != PCF_OK)
+    return r;
+  if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
+                     sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>))) != PCF_OK)
+    return r;
+  const size_t sc_max = 160 * 1024 - 1024;  // scatter launches stay below this
+  if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, SC_TS, PAY>), sc_max)) !=
+      PCF_OK)
+    return r;
+  if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, SC_TS / 2, PAY>),
+                     sc_max)) != PCF_OK)
+    return r;
+  return PCF_OK;
+}
+
+static int set_attrs() {
+  std::lock_guard<std::mutex> g(g_attr_mu);
+  if (g_attr_done) return PCF_OK;
+  int r;
+  if ((r = set_attrs_typed<KT_F64, 0>()) != PCF_OK) return r;
+  if ((r = set_attrs_typed<KT_F64, 1>()) != PCF_OK) return r;
+  if ((r = set_attrs_typed<KT_U64, 0>()) != PCF_OK) return r;
+  if ((r = set_attrs_typed<KT_U64, 1>()) != PCF_OK) return r;
+  g_attr_done = true;
+  return PCF_OK;
+}
+
+int run_sort(const SortArgs& a) {
+  if (a.key_type != PCF_KEY_F64 && a.key_type != PCF_KEY_U64) return PCF_ERR_INVALID_ARGUMENT;
+  if (a.n == 0) {
+    if (a.d_status) PCF_HIP(hipMemsetAsync(a.d_status, 0, sizeof(int32_t), a.stream));
+    return PCF_OK;
+  }
+  if (!a.keys_in) return PCF_ERR_INVALID_ARGUMENT;
+  if (a.n >= (1ull << 32)) return PCF_ERR_INVALID_ARGUMENT;
+  const int has_pay = a.vals_out != nullptr;
+  if (has_pay && !a.iota && !a.vals_in) return PCF_ERR_INVALID_ARGUMENT;
+  if (!has_pay && !a.keys_out) return PCF_ERR_INVALID_ARGUMENT;
+  const pcf_policy pol = current_policy();
+  int r = set_attrs();
+  if (r != PCF_OK) return r;
+  const Layout lay = make_layout(a.n, has_pay, a.nseg, pol, a.keys_out == nullptr,
+                                 a.trace ? a.trace_nb : 0, a.trace ? a.trace_beta : 0);
+  char* ws = reinterpret_cast<char*>(a.ws);
+  bool own = false;
+  if (!ws) {
+    PCF_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), lay.total, a.stream));
+    own = true;
+  } else if (a.ws_bytes < lay.total) {
+    return PCF_ERR_OUT_OF_MEMORY;
+  }
+  int rc;
+  if (a.key_type == PCF_KEY_F64)
+    rc = has_pay ? run_typed<KT_F64, 1>(a, lay, ws, pol) : run_typed<KT_F64, 0>(a, lay, ws, pol);
+  else
+    rc = has_pay ? run_typed<KT_U64, 1>(a, lay, ws, pol) : run_typed<KT_U64, 0>(a, lay, ws, pol);
+  if (own) {
+    hipError_t e = hipFreeAsync(ws, a.stream);
+    if (e != hipSuccess && rc == PCF_OK) rc = hip_fail(e);
+  }
+  return rc;
+}
+
+}  // namespace pcf
+
+using namespace pcf;
+
+extern "C" {
+
+const char* pcf_status_string(int s) {
+  switch (s) {
+    case PCF_OK: return "ok";
+    case PCF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case PCF_ERR_INVALID_KEY: return "invalid key (NaN, infinity or -0.0)";
+    case PCF_ERR_OUT_OF_MEMORY: return "out of memory";
+    case PCF_ERR_HIP: return "HIP runtime error";
+    case PCF_ERR_UNSUPPORTED: return "unsupported";
+    case PCF_PENDING: return "pending";
+    case PCF_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    case PCF_ERR_SHUTDOWN: return "server shutting down";
+    default: return "unknown status";
+  }
+}
+
+int pcf_last_hip_error(void) { return g_last_hip_error; }
+
+const char* pcf_version(void) { return "pcfsort 0.1 (gfx950)"; }
+
+size_t pcf_workspace_bytes(int key_type, size_t n, int with_payload, uint32_t num_segments) {
+  (void)key_type;
+  const pcf_policy pol = current_policy();
+  // argsort may need internal keys: include them
+  return make_layout(n, with_payload, num_segments ? num_segments : 1, pol, with_payload, 0, 0)
+      .total;
+}
+
+int pcf_get_policy(pcf_policy* out) {
+  if (!out) return PCF_ERR_INVALID_ARGUMENT;
+  *out = current_policy();
+  return PCF_OK;
+}
+
+int pcf_set_policy(const pcf_policy* p) {
+  if (!p) return PCF_ERR_INVALID_ARGUMENT;
+  int r = check_policy(*p);
+  if (r != PCF_OK) return r;
+  std::lock_guard<std::mutex> g(g_pol_mu);
+  g_pol = *p;
+  return PCF_OK;
+}
+
+static int sort_keys(int kt, const void* in, void* out, size_t n, void* ws, size_t wsb,
+                     int32_t* d_status, void* stream) {
+  if (n > 0 && (!in || !out)) return PCF_ERR_INVALID_ARGUMENT;
+  SortArgs a = {};
+  a.key_type = kt;
+  a.keys_in = in;
+  a.keys_out = out;
+  a.nseg = 1;
+  a.n = n;
+  a.ws = ws;
+  a.ws_bytes = wsb;
+  a.d_status = d_status;
+  a.stream = reinterpret_cast<hipStream_t>(stream);
+  return run_sort(a);
+}
+
+int pcf_sort_f64(const double* d_in, double* d_out, size_t n, void* d_ws, size_t ws_bytes,
+                 int32_t* d_status, void* stream) {
+  return sort_keys(PCF_KEY_F64, d_in, d_out, n, d_ws, ws_bytes, d_status, stream);
+}
+
+int pcf_sort_u64(const uint64_t* d_in, uint64_t* d_out, size_t n, void* d_ws, size_t ws_bytes,
+                 int32_t* d_status, void* stream) {
+  return sort_keys(PCF_KEY_U64, d_in, d_out, n, d_ws, ws_bytes, d_status, stream);
+}
+
+int pcf_argsort(int key_type, const void* d_keys_in, void* d_keys_out, uint32_t* d_idx_out,
+                size_t n, void* d_ws, size_t ws_bytes, int32_t* d_status, void* stream) {
+  if (n > 0 && (!d_keys_in || !d_idx_out)) return PCF_ERR_INVALID_ARGUMENT;
+  SortArgs a = {};
+  a.key_type = key_type;
+  a.keys_in = d_keys_in;
+  a.keys_out = d_keys_out;
+  a.vals_out = d_idx_out;
+  a.iota = 1;
+  a.nseg = 1;
+  a.n = n;
+  a.ws = d_ws;
+  a.ws_bytes = ws_bytes;
+  a.d_status = d_status;
+  a.stream = reinterpret_cast<hipStream_t>(stream);
+  return run_sort(a);
+}
+
+int pcf_sort_segmented(int key_type, const void* d_keys_in, void* d_keys_out,
+                       const uint32_t* d_vals_in, uint32_t* d_vals_out, const uint64_t* d_offsets,
+                       uint32_t num_segments, size_t total_keys, void* d_ws, size_t ws_bytes,
+                       int32_t* d_status, void* stream) {
+  if (num_segments == 0 || total_keys == 0) return PCF_OK;
+  if (!d_keys_in || !d_keys_out || !d_offsets) return PCF_ERR_INVALID_ARGUMENT;
+  if ((d_vals_in == nullptr) != (d_vals_out == nullptr)) return PCF_ERR_INVALID_ARGUMENT;
+  SortArgs a = {};
+  a.key_type = key_type;
+  a.keys_in = d_keys_in;
+  a.keys_out = d_keys_out;
+  a.vals_in = d_vals_in;
+  a.vals_out = d_vals_out;
+  a.offsets = d_offsets;
+  a.nseg = num_segments;
+  a.n = total_keys;
+  a.ws = d_ws;
+  a.ws_bytes = ws_bytes;
+  a.d_status = d_status;
+  a.stream = reinterpret_cast<hipStream_t>(stream);
+  return run_sort(a);
+}
+
+int pcf_level_trace(int key_type, const void* d_keys_in, const uint32_t* d_vals_in, size_t n,
+                    uint64_t node_seed_v, uint32_t alpha, uint32_t beta, uint32_t gamma,
+                    void* d_part_keys, uint32_t* d_part_vals, uint64_t* h_b, uint64_t* h_T,
+                    uint64_t* h_sizes, uint64_t* h_scalars, void* stream) {
+  if (n == 0 || !d_keys_in || !d_part_keys) return PCF_ERR_INVALID_ARGUMENT;
+  if (alpha == 0 || beta == 0 || beta > MAX_BINS || gamma + 1 > MAX_NB || alpha > (1u << 24))
+    return PCF_ERR_INVALID_ARGUMENT;
+  if ((d_vals_in == nullptr) != (d_part_vals == nullptr)) return PCF_ERR_INVALID_ARGUMENT;
+  SortArgs a = {};
+  a.key_type = key_type;
+  a.keys_in = d_keys_in;
+  a.keys_out = d_part_keys;
+  a.vals_in = d_vals_in;
+  a.vals_out = d_part_vals;
+  a.nseg = 1;
+  a.n = n;
+  a.stream = reinterpret_cast<hipStream_t>(stream);
+  a.trace = 1;
+  a.trace_seed = node_seed_v;
+  a.trace_alpha = alpha;
+  a.trace_beta = beta;
+  a.trace_nb = gamma + 1;
+  a.h_b = h_b;
+  a.h_T = h_T;
+  a.h_sizes = h_sizes;
+  a.h_scalars = h_scalars;
+  int r = run_sort(a);
+  if (r == PCF_OK) {
+    hipError_t e = hipStreamSynchronize(a.stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return r;
+}
+
+}  // extern "C"

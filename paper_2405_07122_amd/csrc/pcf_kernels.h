@@ -1,0 +1,101 @@
+// pcf_kernels.h -- declarations of the gfx950 kernels (defined and explicitly
+// instantiated in pcf_kernels.hip) and the types their launches share with
+// the host driver.
+#pragma once
+
+#include "pcf_device.h"
+
+namespace pcf {
+
+// Creates the roots: one node (or one LDS item) per non-empty segment.
+// offsets == NULL means one segment [0, n).
+struct RootArgs {
+  const void* keys;
+  const uint32_t* vals;
+  const uint64_t* offsets;
+  uint64_t n;
+  uint32_t nseg;
+  uint32_t iota;
+  uint32_t fixed_alpha, fixed_beta, fixed_nb;  // trace: explicit parameters
+  uint32_t force_global;                        // trace: never an LDS item
+  uint64_t fixed_seed;
+  uint32_t has_fixed_seed;
+};
+
+__global__ void k_roots(Plan p, RootArgs a);
+__global__ void k_init(Plan p);
+
+struct LevelIO {
+  void* dst_keys;       // where this level's scatter writes (absolute positions)
+  uint32_t* dst_vals;
+};
+
+// LDS layout of the scatter (bytes), for NW waves and TS keys per tile.
+struct ScatterLds {
+  uint32_t tab, wcnt, runoff, tstart, tcnt, mmlo, mmhi, cmapf, sk, sv, sb, total;
+};
+__host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nbmax, int nw,
+                                                  int ts, int pay) {
+  ScatterLds l;
+  uint32_t o = 0;
+  auto take = [&](uint32_t bytes) {
+    uint32_t r = o;
+    o += (bytes + 15u) & ~15u;
+    return r;
+  };
+  l.tab = take(2u * (max_bins + 1));
+  l.wcnt = take(2u * nw * nbmax);
+  l.runoff = take(4u * nbmax);
+  l.tstart = take(4u * (nbmax + 1));
+  l.tcnt = take(4u * nbmax);
+  l.mmlo = take(8u * nbmax);
+  l.mmhi = take(8u * nbmax);
+  l.cmapf = take(1u * nbmax);
+  l.sk = take(8u * ts);
+  l.sv = take(pay ? 4u * ts : 0u);
+  l.sb = take(2u * ts);
+  l.total = o;
+  return l;
+}
+
+template <int CAP>
+struct K5Cfg {
+  static constexpr uint32_t BMAX = CAP == 8192 ? 861u : CAP == 4096 ? 512u : CAP == 2048 ? 304u
+                                 : CAP == 1024 ? 181u : 0u;
+  static_assert(BMAX > 0, "unsupported LDS capacity");
+  static constexpr uint32_t SMAX = CAP / 16 + 8;
+};
+
+template <int KT, int CAP, int NT>
+struct K5Smem {
+  uint64_t key[CAP];  // key images
+  uint16_t pos[CAP];  // position inside the item
+  uint32_t seg[CAP];  // final segment: start | end << 16
+  uint32_t hist[K5Cfg<CAP>::BMAX + 2];
+  uint32_t cnt[K5Cfg<CAP>::BMAX + 2];
+  uint16_t tab[K5Cfg<CAP>::BMAX + 2];
+  uint32_t stk[K5Cfg<CAP>::SMAX][3];  // start, end, depth | fail << 31
+  uint64_t red64[2 * NT / 64];
+  uint32_t red[NT / 64 + 1];
+  uint32_t nstk;
+  uint32_t item;
+  uint32_t flag;
+  uint32_t sh[4];
+};
+
+template <int KT, int NT>
+__global__ void k_range(Plan p);
+template <int KT, int NT>
+__global__ void k_fit(Plan p, int L, int trace);
+template <int KT, int NT>
+__global__ void k_count(Plan p, int L);
+template <int NT>
+__global__ void k_colscan(Plan p, int L);
+template <int NT>
+__global__ void k_classify(Plan p, int L, LevelIO io);
+template <int KT, int NT, int TS, int PAY>
+__global__ void k_scatter(Plan p, int L, LevelIO io, uint32_t max_bins, uint32_t nbmax);
+template <int KT, int CAP, int NT, int PAY>
+__global__ void k_lds_sort(Plan p, int cls);
+
+}  // namespace pcf

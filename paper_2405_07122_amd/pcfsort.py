@@ -1,0 +1,296 @@
+"""Python binding of libpcfsort.so (ctypes; argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/pcfsort.h with
+the same name.  Device buffers are torch tensors on a ROCm device (torch is
+used only for memory and streams); every step of the sort runs in the
+library's HIP kernels.  There is no CPU fallback: if the library or a GPU is
+missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcfsort.so")
+
+OK = 0
+ERR_INVALID_ARGUMENT = 1
+ERR_INVALID_KEY = 2
+ERR_OUT_OF_MEMORY = 3
+ERR_HIP = 4
+ERR_UNSUPPORTED = 5
+PENDING = 6
+ERR_UNKNOWN_TICKET = 7
+ERR_SHUTDOWN = 8
+
+KEY_F64 = 0
+KEY_U64 = 1
+
+EXPORTS = [
+    "pcf_status_string", "pcf_last_hip_error", "pcf_version", "pcf_workspace_bytes",
+    "pcf_sort_f64", "pcf_sort_u64", "pcf_argsort", "pcf_sort_segmented", "pcf_level_trace",
+    "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
+    "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
+    "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
+]
+
+
+class PcfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib
+        msg = lib.pcf_status_string(code).decode() if lib is not None else str(code)
+        if code == ERR_HIP and lib is not None:
+            msg += f" (hipError {lib.pcf_last_hip_error()})"
+        super().__init__(f"{where}: {msg}")
+        self.code = code
+
+
+class Policy(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint32) for name in (
+        "max_buckets", "target_child", "bins_per_bucket", "max_bins", "samples_per_bucket",
+        "max_samples", "chunk_keys", "lds_cap", "tau", "seed")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_streams", ctypes.c_uint32),
+                ("max_batch_requests", ctypes.c_uint32), ("max_batch_keys", ctypes.c_uint64),
+                ("device", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class ServeResult(ctypes.Structure):
+    _fields_ = [("d_keys_sorted", ctypes.c_void_p), ("d_idx", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("latency_ns", ctypes.c_uint64),
+                ("queue_ns", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("batch_requests", ctypes.c_uint32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "released", "batches", "budget_bytes", "budget_in_use",
+        "budget_high_water", "queued")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+_I32 = ctypes.c_int32
+_INT = ctypes.c_int
+
+
+def load(path: str = LIB_PATH):
+    """Loads libpcfsort.so; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run paper_2405_07122_amd/build.py "
+                          f"(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "pcf_status_string": (ctypes.c_char_p, [_INT]),
+        "pcf_last_hip_error": (_INT, []),
+        "pcf_version": (ctypes.c_char_p, []),
+        "pcf_workspace_bytes": (_SZ, [_INT, _SZ, _INT, _U32]),
+        "pcf_sort_f64": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+        "pcf_sort_u64": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+        "pcf_argsort": (_INT, [_INT, _VP, _VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+        "pcf_sort_segmented": (_INT, [_INT, _VP, _VP, _VP, _VP, _VP, _U32, _SZ, _VP, _SZ, _VP,
+                                      _VP]),
+        "pcf_level_trace": (_INT, [_INT, _VP, _VP, _SZ, _U64, _U32, _U32, _U32, _VP, _VP, _VP,
+                                   _VP, _VP, _VP, _VP]),
+        "pcf_get_policy": (_INT, [ctypes.POINTER(Policy)]),
+        "pcf_set_policy": (_INT, [ctypes.POINTER(Policy)]),
+        "pcf_autotune": (_INT, [_INT, _INT, ctypes.c_char_p]),
+        "pcf_load_tuning": (_INT, [ctypes.c_char_p]),
+        "pcf_serve_create": (_INT, [ctypes.POINTER(ServeConfig), ctypes.POINTER(_VP)]),
+        "pcf_serve_submit": (_INT, [_VP, _INT, _VP, _SZ, _INT, ctypes.POINTER(_U64)]),
+        "pcf_serve_poll": (_INT, [_VP, _U64, ctypes.POINTER(ServeResult)]),
+        "pcf_serve_wait": (_INT, [_VP, _U64, _U32, ctypes.POINTER(ServeResult)]),
+        "pcf_serve_release": (_INT, [_VP, _U64]),
+        "pcf_serve_get_stats": (_INT, [_VP, ctypes.POINTER(ServeStats)]),
+        "pcf_serve_destroy": (_INT, [_VP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise PcfError(rc, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _key_type(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return KEY_F64
+    if t.dtype in (torch.int64, torch.uint64):
+        return KEY_U64  # 64-bit unsigned keys may travel in an int64 tensor
+    raise TypeError(f"keys must be float64 or (u)int64, got {t.dtype}")
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("tensors must be contiguous and on a ROCm device")
+
+
+def version() -> str:
+    return load().pcf_version().decode()
+
+
+def workspace_bytes(key_type: int, n: int, with_payload: bool = False, num_segments: int = 1) -> int:
+    return int(load().pcf_workspace_bytes(key_type, n, int(with_payload), num_segments))
+
+
+def workspace(key_type: int, n: int, with_payload: bool = False, num_segments: int = 1,
+              device=None) -> torch.Tensor:
+    """A device workspace tensor large enough for the given sort."""
+    nb = workspace_bytes(key_type, n, with_payload, num_segments)
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def _ws_args(ws):
+    if ws is None:
+        return None, 0
+    return _ptr(ws), ws.numel() * ws.element_size()
+
+
+def pcf_sort_f64(keys: torch.Tensor, out: torch.Tensor | None = None, ws=None, d_status=None,
+                 stream=None) -> torch.Tensor:
+    lib = load()
+    if keys.dtype != torch.float64:
+        raise TypeError("pcf_sort_f64 needs float64 keys")
+    out = torch.empty_like(keys) if out is None else out
+    _need_cuda(keys, out)
+    wp, wb = _ws_args(ws)
+    _check(lib.pcf_sort_f64(_ptr(keys), _ptr(out), keys.numel(), wp, wb, _ptr(d_status),
+                            _stream(stream)), "pcf_sort_f64")
+    return out
+
+
+def pcf_sort_u64(keys: torch.Tensor, out: torch.Tensor | None = None, ws=None, d_status=None,
+                 stream=None) -> torch.Tensor:
+    lib = load()
+    if keys.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("pcf_sort_u64 needs 64-bit integer keys (read as unsigned)")
+    out = torch.empty_like(keys) if out is None else out
+    _need_cuda(keys, out)
+    wp, wb = _ws_args(ws)
+    _check(lib.pcf_sort_u64(_ptr(keys), _ptr(out), keys.numel(), wp, wb, _ptr(d_status),
+                            _stream(stream)), "pcf_sort_u64")
+    return out
+
+
+def sort(keys: torch.Tensor, out=None, ws=None, d_status=None, stream=None) -> torch.Tensor:
+    if _key_type(keys) == KEY_F64:
+        return pcf_sort_f64(keys, out, ws, d_status, stream)
+    return pcf_sort_u64(keys, out, ws, d_status, stream)
+
+
+def pcf_argsort(keys: torch.Tensor, keys_out: torch.Tensor | None = None,
+                idx_out: torch.Tensor | None = None, ws=None, d_status=None, stream=None,
+                want_keys: bool = True):
+    """Stable argsort: returns (sorted keys or None, int32 tensor of input positions
+    holding uint32 values)."""
+    lib = load()
+    kt = _key_type(keys)
+    n = keys.numel()
+    if keys_out is None and want_keys:
+        keys_out = torch.empty_like(keys)
+    if idx_out is None:
+        idx_out = torch.empty(n, dtype=torch.int32, device=keys.device)
+    _need_cuda(keys, keys_out, idx_out)
+    wp, wb = _ws_args(ws)
+    _check(lib.pcf_argsort(kt, _ptr(keys), _ptr(keys_out), _ptr(idx_out), n, wp, wb,
+                           _ptr(d_status), _stream(stream)), "pcf_argsort")
+    return keys_out, idx_out
+
+
+def pcf_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor | None = None,
+                       keys_out=None, vals_out=None, ws=None, d_status=None, stream=None):
+    """Each CSR segment [offsets[s], offsets[s+1]) sorted on its own, stably,
+    carrying `vals` (int32 tensor holding uint32 words).  offsets: int64 device
+    tensor of num_segments + 1 entries."""
+    lib = load()
+    kt = _key_type(keys)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    _need_cuda(keys, offsets, vals, keys_out, vals_out)
+    nseg = offsets.numel() - 1
+    wp, wb = _ws_args(ws)
+    _check(lib.pcf_sort_segmented(kt, _ptr(keys), _ptr(keys_out), _ptr(vals), _ptr(vals_out),
+                                  _ptr(offsets), nseg, keys.numel(), wp, wb, _ptr(d_status),
+                                  _stream(stream)), "pcf_sort_segmented")
+    return keys_out, vals_out
+
+
+def pcf_level_trace(keys: torch.Tensor, alpha: int, beta: int, gamma: int, node_seed: int,
+                    vals: torch.Tensor | None = None, stream=None) -> dict:
+    """One model-based bucketing on the GPU with explicit parameters; returns
+    the model (b, T), bucket sizes and the stable partition."""
+    import numpy as np
+    lib = load()
+    kt = _key_type(keys)
+    part = torch.empty_like(keys)
+    pvals = torch.empty_like(vals) if vals is not None else None
+    _need_cuda(keys, vals)
+    hb = np.zeros(beta + 1, dtype=np.uint64)
+    hT = np.zeros(beta + 1, dtype=np.uint64)
+    hs = np.zeros(gamma + 1, dtype=np.uint64)
+    sc = np.zeros(5, dtype=np.uint64)
+    _check(lib.pcf_level_trace(kt, _ptr(keys), _ptr(vals), keys.numel(), node_seed, alpha, beta,
+                               gamma, _ptr(part), _ptr(pvals), hb.ctypes.data, hT.ctypes.data,
+                               hs.ctypes.data, sc.ctypes.data, _stream(stream)),
+           "pcf_level_trace")
+    return {"b": hb, "T": hT, "sizes": hs, "min_bits": int(sc[0]), "max_bits": int(sc[1]),
+            "scale_bits": int(sc[2]), "halves": int(sc[3]), "status": int(sc[4]),
+            "part_keys": part, "part_vals": pvals}
+
+
+def get_policy() -> dict:
+    p = Policy()
+    _check(load().pcf_get_policy(ctypes.byref(p)), "pcf_get_policy")
+    return p.as_dict()
+
+
+def set_policy(**kw) -> dict:
+    p = Policy()
+    lib = load()
+    _check(lib.pcf_get_policy(ctypes.byref(p)), "pcf_get_policy")
+    for k, v in kw.items():
+        setattr(p, k, int(v))
+    _check(lib.pcf_set_policy(ctypes.byref(p)), "pcf_set_policy")
+    return p.as_dict()
+
+
+def pcf_autotune(key_type: int, with_payload: bool, out_json: str) -> None:
+    _check(load().pcf_autotune(key_type, int(with_payload), out_json.encode()), "pcf_autotune")
+
+
+def pcf_load_tuning(path: str) -> None:
+    _check(load().pcf_load_tuning(path.encode()), "pcf_load_tuning")

@@ -1,0 +1,128 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every comparison is exact: the sorted order of keys without NaN / -0.0 is
+unique, argsort ties break by position, and one bucketing level with the same
+parameters and node seed must reproduce the oracle's model (b, T), bucket sizes
+and stable partition exactly (both sides round the fp64 bin function the same
+way)."""
+import numpy as np
+import pytest
+
+from paper_2405_07122_amd import datagen
+from tests.gpu_util import banner, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_07122_amd import pcfsort
+    pcfsort.load()
+    return pcfsort
+
+
+def _dt(x):
+    return np.float64 if x.dtype == np.float64 else np.uint64
+
+
+LEVEL_CASES = [
+    ("uniform", lambda: datagen.f64("uniform", 200_000, 31), (4096, 8192, 511)),
+    ("lognormal", lambda: datagen.f64("lognormal", 150_000, 32), (2000, 16000, 1023)),
+    ("normal-ragged", lambda: datagen.f64("normal", 99_991, 33), (777, 3001, 300)),
+    ("zipf-u64", lambda: datagen.u64("zipf", 120_000, 34, distinct=5000), (3000, 5000, 255)),
+    ("bursty-u64", lambda: datagen.u64("bursty", 100_003, 35), (1500, 4000, 2047)),
+    ("two-valued", lambda: np.where(np.random.default_rng(3).random(50_000) < 0.4, 1.5, -2.25),
+     (500, 700, 63)),
+]
+
+
+@pytest.mark.parametrize("name,gen,params", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
+def test_level_trace_matches_oracle(P, oracle, name, gen, params):
+    x = gen()
+    alpha, beta, gamma = params
+    banner(f"level trace {name} n={x.shape[0]} alpha={alpha} beta={beta} gamma={gamma}")
+    nseed = oracle.node_seed(7, 0, 0, 0)
+    idx = np.arange(x.shape[0], dtype=np.uint32)
+    ref = oracle.level(x, alpha, beta, gamma, nseed, vals=idx)
+    got = P.pcf_level_trace(to_dev(x), alpha, beta, gamma, nseed, vals=to_dev(idx))
+    assert got["status"] == ref.status
+    assert got["min_bits"] == ref.min_bits and got["max_bits"] == ref.max_bits
+    assert got["scale_bits"] == np.float64(ref.scale).view(np.uint64)
+    assert got["halves"] == ref.halves
+    np.testing.assert_array_equal(got["b"], ref.b)
+    np.testing.assert_array_equal(got["T"], ref.T)
+    np.testing.assert_array_equal(got["sizes"], ref.sizes)
+    np.testing.assert_array_equal(to_host(got["part_keys"], _dt(x)), ref.part_keys)
+    np.testing.assert_array_equal(to_host(got["part_vals"], np.uint32), ref.part_vals)
+
+
+SIZES = [1, 2, 3, 99, 100, 101, 2047, 2048, 2049, 8191, 8192, 8193, 12_345, 65_537, 300_001]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_sizes_f64(P, oracle, n):
+    banner(f"sort f64 uniform n={n}")
+    x = datagen.f64("normal", n, 1000 + n)
+    ref, _, _ = oracle.sort(x)
+    got = to_host(P.pcf_sort_f64(to_dev(x)), np.float64)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_config1_bit_exact(P, oracle):
+    banner("config1: n=1e6 fp64 uniform seed 0")
+    x = datagen.config1()
+    ref, _, _ = oracle.sort(x)
+    got = to_host(P.pcf_sort_f64(to_dev(x)), np.float64)
+    np.testing.assert_array_equal(got, ref)
+    np.testing.assert_array_equal(got, np.sort(x))
+
+
+@pytest.mark.parametrize("dist", datagen.F64_DISTS)
+def test_argsort_f64(P, oracle, dist):
+    n = 400_000
+    banner(f"argsort f64 {dist} n={n}")
+    x = datagen.f64(dist, n, 77)
+    x = np.round(x, 3) + 0.0  # duplicates, so ties matter
+    ks, idx, _ = oracle.argsort(x)
+    gk, gi = P.pcf_argsort(to_dev(x))
+    np.testing.assert_array_equal(to_host(gk, np.float64), ks)
+    np.testing.assert_array_equal(to_host(gi, np.uint32), idx)
+
+
+@pytest.mark.parametrize("kind", datagen.U64_KINDS)
+def test_sort_u64(P, oracle, kind):
+    n = 500_000
+    banner(f"sort u64 {kind} n={n}")
+    x = datagen.u64(kind, n, 88, distinct=20_000)
+    ref, _, _ = oracle.sort(x)
+    got = to_host(P.pcf_sort_u64(to_dev(x)), np.uint64)
+    np.testing.assert_array_equal(got, ref)
+    ks, idx, _ = oracle.argsort(x)
+    gk, gi = P.pcf_argsort(to_dev(x))
+    np.testing.assert_array_equal(to_host(gi, np.uint32), idx)
+
+
+def test_invalid_keys(P):
+    for bad in (np.nan, np.inf, -np.inf, -0.0):
+        for n in (50, 5000, 100_000):
+            banner(f"invalid key {bad} n={n}")
+            x = datagen.f64("uniform", n, 5)
+            x[n // 2] = bad
+            with pytest.raises(P.PcfError) as e:
+                P.pcf_sort_f64(to_dev(x))
+            assert e.value.code == P.ERR_INVALID_KEY
+
+
+def test_in_place_and_all_equal(P, oracle):
+    import torch
+    banner("in place + all equal")
+    x = datagen.f64("exponential", 250_000, 9)
+    t = to_dev(x)
+    P.pcf_sort_f64(t, out=t)
+    np.testing.assert_array_equal(to_host(t, np.float64), np.sort(x))
+    y = np.full(300_000, 3.5)
+    _, gi = P.pcf_argsort(to_dev(y))
+    np.testing.assert_array_equal(to_host(gi, np.uint32), np.arange(300_000, dtype=np.uint32))
