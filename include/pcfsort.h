@@ -129,6 +129,37 @@ int pcf_level_trace(int key_type, const void *d_keys_in, const uint32_t *d_vals_
                     void *d_part_keys, uint32_t *d_part_vals, uint64_t *h_b, uint64_t *h_T,
                     uint64_t *h_sizes, uint64_t *h_scalars, void *stream);
 
+/* ---- per-kernel profile -------------------------------------------------
+ * When enabled, every later sort call records hipEvents around each of its
+ * kernel launches on its stream, waits for its stream at the end, and adds
+ * the elapsed times and the number of keys each launch processed to
+ * process-wide counters.  Used by the benchmark to price each kernel against
+ * the HBM roofline.  Not thread-safe with respect to concurrent calls.
+ */
+typedef enum {
+    PCF_K_SETUP = 0,    /* control block + roots */
+    PCF_K_RANGE = 1,    /* minimum / maximum of the top-level arrays */
+    PCF_K_FIT = 2,      /* samples, histogram, prefix, bin -> bucket table */
+    PCF_K_COUNT = 3,    /* bucket counts per chunk */
+    PCF_K_COLSCAN = 4,  /* scan of the counts over chunks */
+    PCF_K_CLASSIFY = 5, /* bucket starts, recurse / standard-sort decision */
+    PCF_K_SCATTER = 6,  /* stable scatter into contiguous buckets */
+    PCF_K_LDS_SMALL = 7,/* in-LDS finish, arrays of up to 2048 keys */
+    PCF_K_LDS_BIG = 8,  /* in-LDS finish, arrays of up to 8192 keys */
+    PCF_K_COUNT_KINDS = 9
+} pcf_kernel_kind;
+
+typedef struct {
+    uint64_t launches;
+    double ms;    /* summed hipEvent elapsed time */
+    double keys;  /* summed keys processed by the launches */
+} pcf_kernel_stat;
+
+int pcf_profile_enable(int on);
+/* Copies PCF_K_COUNT_KINDS entries into out; reset != 0 clears the counters. */
+int pcf_profile_read(pcf_kernel_stat *out, int reset);
+const char *pcf_kernel_name(int kind);
+
 /* ---- policy (parameters of the GPU recursion) ---------------------------- */
 
 /*

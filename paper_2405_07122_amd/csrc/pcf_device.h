@@ -153,23 +153,31 @@ enum : uint32_t { NK_PCF = 0, NK_RADIX = 1 };
 enum : uint32_t { NS_ACTIVE = 0, NS_DONE = 1 };
 enum : uint32_t { IF_STD = 1, IF_ROOT = 2, IF_IOTA = 4 };
 
-// One array of a global level (a node of the recursion tree).
+// Minimum and maximum key image of part of an array.
+struct MinMax {
+  uint64_t lo, hi;
+};
+
+// One array of a global level (a node of the recursion tree).  Its producer
+// (the roots kernel or the parent's classify kernel) fills everything above
+// `state`, including the parameters and the arena offsets; the fit kernel
+// fills the rest.
 struct Node {
   const void* src;          // keys of the node, element 0
   const uint32_t* vsrc;     // payload of the node, element 0 (NULL: none or iota)
+  const MinMax* mmp;        // partial ranges to reduce into [min_img, max_img]
   uint64_t off;             // absolute position of element 0 in the output
   uint64_t rel;             // position inside its segment (names the node)
   uint64_t seed;            // sampling seed of the node
-  unsigned long long min_img, max_img;  // key range (reduced by the producer)
+  uint64_t table_off, cm_off;  // arena offsets (u16 table, u32 count matrix)
   uint32_t len, seg, depth, kind;
-  uint32_t nchunks, unit_base;
-  uint32_t fixed;           // alpha / beta / nb preset by the caller
+  uint32_t nchunks, unit_base, aux_off, mmn;
+  uint32_t nb, nbits, beta, alpha, delta;
   uint32_t iota;            // payload is the position inside the segment
   // filled by the fit kernel
-  uint32_t state, nb, nbits, beta, alpha, delta, shift, halves;
+  uint32_t state, shift, halves, pad;
+  uint64_t min_img, max_img;
   double scale;
-  uint64_t table_off, cm_off;
-  uint32_t aux_off, task_base;
 };
 
 struct Unit {
@@ -186,24 +194,30 @@ struct Item {
 };
 
 struct LevelCtr {
-  uint32_t num_nodes, num_units, tasks, aux_used;
+  uint32_t num_nodes, num_units, aux_used, pad;
   unsigned long long table_used, cm_used;
+  unsigned long long keys;  // keys in the level's nodes
 };
 
 struct Ctl {
   int32_t status;      // 0 or the data error (PCF_ERR_INVALID_KEY)
   uint32_t overflow;   // a capacity bound was exceeded (library bug guard)
-  uint32_t item_count[2];
-  uint32_t item_next[2];
-  uint32_t n_radix_nodes, n_fail_items, n_done_nodes, pad;
+  uint32_t item_count[3];
+  uint32_t n_radix_nodes, n_fail_items, n_done_nodes;
+  unsigned long long item_keys[3];  // keys in the LDS items of each class (profiling)
   LevelCtr lv[MAX_LEVELS];
 };
 
 struct PolicyDev {
   uint32_t max_buckets, target_child, bins_per_bucket, max_bins;
   uint32_t samples_per_bucket, max_samples, chunk_keys, lds_cap;
-  uint32_t tau, small_cap, seed_lo, seed_hi;
+  uint32_t tau, small_cap, prof, mid_cap;
 };
+
+// LDS-finish class of an array of `len` keys (0: <= small_cap, 1: <= mid_cap, 2: larger).
+__device__ __host__ inline int item_class(uint32_t len, const PolicyDev& pol) {
+  return len <= pol.small_cap ? 0 : (len <= pol.mid_cap ? 1 : 2);
+}
 
 // Everything a kernel of one call needs (passed by value).
 struct Plan {
@@ -218,19 +232,49 @@ struct Plan {
   Unit* units[2];
   uint16_t* table[2];
   uint32_t* cm[2];
+  MinMax* mm[2];        // per (bucket, chunk) ranges written by the scatter
   uint32_t* bstart[2];
   int32_t* cmap[2];
   uint32_t* task_node[2];
-  uint32_t cap_nodes, cap_units, cap_tasks, cap_aux;
+  MinMax* mmr;          // per-unit ranges of the roots (range kernel)
+  uint32_t cap_nodes, cap_units, cap_aux, pad;
   unsigned long long cap_table, cap_cm;
-  Item* items[2];
-  uint32_t cap_items[2];
+  Item* items[3];
+  uint32_t cap_items[3];
   // trace (level 0 only): prefix counts b of node 0
   uint32_t* trace_b;
   PolicyDev pol;
   uint64_t seed;
   uint64_t n_total;  // keys in the whole call (bound of every output position)
 };
+
+// Parameters of a node of `len` keys (gamma + 1 = nb buckets, beta bins,
+// alpha samples, failure threshold delta; Sec. 3.3 and the policy).
+__device__ __host__ inline void node_params(uint32_t len, uint32_t kind, const PolicyDev& pol,
+                                            uint32_t& nb, uint32_t& beta, uint32_t& alpha,
+                                            uint32_t& delta) {
+  if (kind == NK_RADIX) {
+    nb = RADIX_NB;
+    beta = 0;
+    alpha = 0;
+    delta = 0xffffffffu;
+    return;
+  }
+  const uint32_t tgt = (len + pol.target_child - 1) / pol.target_child;
+  nb = 2;
+  while (nb < tgt && nb < pol.max_buckets) nb <<= 1;
+  beta = pol.bins_per_bucket * nb;
+  if (beta > pol.max_bins) beta = pol.max_bins;
+  alpha = pol.samples_per_bucket * nb;
+  if (alpha > pol.max_samples) alpha = pol.max_samples;
+  delta = root34(len);
+}
+
+__device__ __host__ inline uint32_t bits_for(uint32_t nb) {
+  uint32_t b = 0;
+  while ((1u << b) < nb) ++b;
+  return b;
+}
 
 // Ctl::overflow bits
 constexpr uint32_t OVF_CAPACITY = 1;  // a work-list bound was exceeded

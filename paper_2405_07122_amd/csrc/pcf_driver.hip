@@ -19,6 +19,18 @@
 #include "pcf_driver.h"
 #include "pcf_kernels.h"
 
+// Compile-time variants (defaults: the measured best on MI355X):
+//   PCF_KEYS_SCATTER 0: keys-only levels use the generic scatter kernel;
+//                    1: the three-barrier keys-only kernel, 4096-key tiles;
+//                    2: the same with 8192-key tiles.
+//   PCF_K5_CLASSES   2: LDS-finish classes <= 2048 and <= 8192 keys; 3: adds <= 4096.
+#ifndef PCF_KEYS_SCATTER
+#define PCF_KEYS_SCATTER 0
+#endif
+#ifndef PCF_K5_CLASSES
+#define PCF_K5_CLASSES 3
+#endif
+
 namespace pcf {
 
 static thread_local int g_last_hip_error = 0;
@@ -33,10 +45,10 @@ int hip_fail(hipError_t e, const char* what, int line) {
 
 static std::mutex g_pol_mu;
 static pcf_policy g_pol = {
-    /*max_buckets*/ 1024,
+    /*max_buckets*/ 256,
     /*target_child*/ 2048,
     /*bins_per_bucket*/ 16,
-    /*max_bins*/ 16383,
+    /*max_bins*/ 4096,
     /*samples_per_bucket*/ 16,
     /*max_samples*/ 65536,
     /*chunk_keys*/ 16384,
@@ -77,11 +89,79 @@ int device_cus() {
   return g_cus;
 }
 
-// K5 sizes of the two item classes (LDS capacity and workgroup size).
+// ---- opt-in per-kernel profile ---------------------------------------------
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static pcf_kernel_stat g_prof[PCF_K_COUNT_KINDS];
+
+struct ProfMark {
+  int kind, level;
+  hipEvent_t a, b;
+};
+
+// Event pairs of one call; events are pooled per thread.
+struct CallProf {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<ProfMark> marks;
+  size_t used = 0;
+  int begin(int kind, int level) {
+    if (!on) return PCF_OK;
+    if (used == marks.size()) {
+      ProfMark m = {kind, level, nullptr, nullptr};
+      PCF_HIP(hipEventCreate(&m.a));
+      PCF_HIP(hipEventCreate(&m.b));
+      marks.push_back(m);
+    }
+    marks[used].kind = kind;
+    marks[used].level = level;
+    PCF_HIP(hipEventRecord(marks[used].a, st));
+    return PCF_OK;
+  }
+  int end() {
+    if (!on) return PCF_OK;
+    PCF_HIP(hipEventRecord(marks[used].b, st));
+    ++used;
+    return PCF_OK;
+  }
+  // after the stream is synchronized: fold the marks into the global counters
+  int commit(const Ctl& hc, uint64_t n) {
+    if (!on) return PCF_OK;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0.f;
+      PCF_HIP(hipEventElapsedTime(&ms, marks[i].a, marks[i].b));
+      const int k = marks[i].kind, L = marks[i].level;
+      double keys = 0;
+      if (k == PCF_K_SETUP) keys = (double)n;
+      else if (k == PCF_K_LDS_SMALL) keys = (double)hc.item_keys[0];
+      else if (k == PCF_K_LDS_BIG) keys = (double)(hc.item_keys[1] + hc.item_keys[2]);
+      else keys = (double)hc.lv[L].keys;
+      g_prof[k].launches += 1;
+      g_prof[k].ms += ms;
+      g_prof[k].keys += keys;
+    }
+    used = 0;
+    return PCF_OK;
+  }
+};
+static thread_local CallProf t_prof;
+
+#define PCF_MARK(kind, level, launch)                 \
+  do {                                                \
+    int r_ = t_prof.begin((kind), (level));           \
+    if (r_ != PCF_OK) return r_;                      \
+    launch;                                           \
+    r_ = t_prof.end();                                \
+    if (r_ != PCF_OK) return r_;                      \
+  } while (0)
+
+// LDS-finish classes (LDS capacity and workgroup size).
 constexpr int K5_SMALL_CAP = 2048, K5_SMALL_NT = 256;
+constexpr int K5_MID_CAP = 4096, K5_MID_NT = 256;
 constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = 512;
-// Scatter tile.
-constexpr int SC_NT = 512, SC_TS = 4096;
+// Scatter workgroup and tile: keys only (unstable ranks) / with a payload (stable).
+constexpr int SC_NT = 512, SC_TS_KEYS = 8192, SC_TS_PAY = 4096;
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -116,14 +196,15 @@ Layout make_layout(size_t n, int has_pay, uint32_t nseg, const pcf_policy& pol, 
   const uint64_t half = std::max<uint64_t>(pol.lds_cap / 4, 1);  // small_cap / 2
   const uint64_t items0 = 2 * n / half + 2 * n / 700 + 2 * MAX_LEVELS * nodes + nseg + 1024;
   const uint64_t items1 = n / (K5_SMALL_CAP + 1) + nseg + 1024;
+  const uint64_t items2 = n / (K5_MID_CAP + 1) + nseg + 1024;
   L.cap_nodes = (uint32_t)std::min<uint64_t>(nodes, 0xffffffffu);
   L.cap_units = (uint32_t)std::min<uint64_t>(units, 0xffffffffu);
   L.cap_aux = (uint32_t)std::min<uint64_t>(aux, 0xffffffffu);
-  L.cap_tasks = L.cap_aux;
   L.cap_table = table;
   L.cap_cm = cmc;
   L.cap_items[0] = (uint32_t)std::min<uint64_t>(items0, 0xffffffffu);
   L.cap_items[1] = (uint32_t)std::min<uint64_t>(items1, 0xffffffffu);
+  L.cap_items[2] = (uint32_t)std::min<uint64_t>(items2, 0xffffffffu);
   L.nbmax = (uint32_t)nbmax;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -136,17 +217,18 @@ Layout make_layout(size_t n, int has_pay, uint32_t nseg, const pcf_policy& pol, 
   L.tmp_vals = take(has_pay ? n * 4 : 0);
   L.int_keys = take(int_keys ? n * 8 : 0);
   L.trace_b = take(trace_beta ? 4ull * (trace_beta + 1) : 0);
+  L.mmr = take(sizeof(MinMax) * (size_t)L.cap_units);
   for (int s = 0; s < 2; ++s) {
     L.nodes[s] = take(sizeof(Node) * (size_t)L.cap_nodes);
     L.units[s] = take(sizeof(Unit) * (size_t)L.cap_units);
     L.table[s] = take(2 * (size_t)L.cap_table);
     L.cm[s] = take(4 * (size_t)L.cap_cm);
+    L.mm[s] = take(sizeof(MinMax) * (size_t)L.cap_cm);
     L.bstart[s] = take(4 * (size_t)L.cap_aux);
     L.cmap[s] = take(4 * (size_t)L.cap_aux);
-    L.task_node[s] = take(4 * (size_t)L.cap_tasks);
+    L.task_node[s] = take(4 * (size_t)L.cap_aux);
   }
-  L.items[0] = take(sizeof(Item) * (size_t)L.cap_items[0]);
-  L.items[1] = take(sizeof(Item) * (size_t)L.cap_items[1]);
+  for (int k = 0; k < 3; ++k) L.items[k] = take(sizeof(Item) * (size_t)L.cap_items[k]);
   L.total = o;
   return L;
 }
@@ -184,25 +266,48 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     p.units[s] = reinterpret_cast<Unit*>(ws + lay.units[s]);
     p.table[s] = reinterpret_cast<uint16_t*>(ws + lay.table[s]);
     p.cm[s] = reinterpret_cast<uint32_t*>(ws + lay.cm[s]);
+    p.mm[s] = reinterpret_cast<MinMax*>(ws + lay.mm[s]);
     p.bstart[s] = reinterpret_cast<uint32_t*>(ws + lay.bstart[s]);
     p.cmap[s] = reinterpret_cast<int32_t*>(ws + lay.cmap[s]);
     p.task_node[s] = reinterpret_cast<uint32_t*>(ws + lay.task_node[s]);
-    p.items[s] = reinterpret_cast<Item*>(ws + lay.items[s]);
-    p.cap_items[s] = lay.cap_items[s];
   }
+  for (int k = 0; k < 3; ++k) {
+    p.items[k] = reinterpret_cast<Item*>(ws + lay.items[k]);
+    p.cap_items[k] = lay.cap_items[k];
+  }
+  p.mmr = reinterpret_cast<MinMax*>(ws + lay.mmr);
   p.cap_nodes = lay.cap_nodes;
   p.cap_units = lay.cap_units;
-  p.cap_tasks = lay.cap_tasks;
   p.cap_aux = lay.cap_aux;
   p.cap_table = lay.cap_table;
   p.cap_cm = lay.cap_cm;
   p.trace_b = a.trace ? reinterpret_cast<uint32_t*>(ws + lay.trace_b) : nullptr;
   // scatter work per level: enough units to give every workgroup a few
   const uint32_t bins_lds = std::max<uint32_t>(pol.max_bins, a.trace ? a.trace_beta : 0u);
-  ScatterLds sl = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, SC_TS, PAY);
-  const bool small_tile = sl.total > 160 * 1024 - 1024;  // many buckets: halve the tile
-  if (small_tile) sl = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, SC_TS / 2, PAY);
-  if (sl.total > 160 * 1024 - 1024) return PCF_ERR_INVALID_ARGUMENT;
+  // keys only: the LDS-atomic scatter; with a payload: the stable one
+  static const bool big_keys_tile = getenv("PCF_SCATTER_KEYS_TILE_8K") != nullptr;
+  int sc_ts;
+  uint32_t sc_lds;
+  if (PAY) {
+    sc_ts = SC_TS_PAY;
+    sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY).total;
+    if (sc_lds > 160 * 1024 - 1024) {  // many buckets: halve the tile
+      sc_ts /= 2;
+      sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY).total;
+    }
+  } else {
+    sc_ts = (big_keys_tile || PCF_KEYS_SCATTER == 2) ? 8192 : 4096;
+    sc_lds = PCF_KEYS_SCATTER == 0 ? scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, 4096, 0).total
+                                   : scatter_keys_lds(bins_lds, lay.nbmax, sc_ts).total;
+    if (sc_lds > 160 * 1024 - 1024) {
+      sc_ts = 4096;
+      sc_lds = scatter_keys_lds(bins_lds, lay.nbmax, sc_ts).total;
+    }
+  }
+  if (sc_lds > 160 * 1024 - 1024) return PCF_ERR_INVALID_ARGUMENT;
+  struct {
+    uint32_t total;
+  } sl = {sc_lds};
   const int sc_per_cu = std::max(1, (int)(160 * 1024 / sl.total));
   const int g_sc = cus * std::min(sc_per_cu, 2);
   PolicyDev pd;
@@ -212,12 +317,16 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   pd.max_bins = pol.max_bins;
   pd.samples_per_bucket = pol.samples_per_bucket;
   pd.max_samples = pol.max_samples;
-  pd.chunk_keys = (uint32_t)std::max<uint64_t>(pol.chunk_keys, (a.n + 4ull * g_sc - 1) / (4ull * g_sc));
+  pd.chunk_keys =
+      (uint32_t)std::max<uint64_t>(pol.chunk_keys, (a.n + 8ull * g_sc - 1) / (8ull * g_sc));
   pd.lds_cap = pol.lds_cap;
   pd.tau = pol.tau;
   pd.small_cap = K5_SMALL_CAP;
-  pd.seed_lo = pol.seed;
-  pd.seed_hi = 0;
+  pd.mid_cap = PCF_K5_CLASSES == 2 ? K5_SMALL_CAP : K5_MID_CAP;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    pd.prof = g_prof_on ? 1u : 0u;
+  }
   p.pol = pd;
   p.seed = (uint64_t)pol.seed;
   p.n_total = a.n;
@@ -251,9 +360,18 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     vdst[1] = (vdst[0] == a.vals_out) ? tmp_vals : a.vals_out;
   }
 
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, p);
-  hipLaunchKernelGGL(k_roots, dim3((a.nseg + 255) / 256), dim3(256), 0, st, p, ra);
-  hipLaunchKernelGGL((k_range<KT, 256>), dim3(cus * 8), dim3(256), 0, st, p);
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    t_prof.on = g_prof_on;
+  }
+  t_prof.st = st;
+  t_prof.used = 0;
+  PCF_MARK(PCF_K_SETUP, 0, {
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_roots, dim3(1), dim3(1024), 0, st, p, ra);
+  });
+  PCF_MARK(PCF_K_RANGE, 0,
+           hipLaunchKernelGGL((k_range<KT, 256>), dim3(cus * 8), dim3(256), 0, st, p));
   PCF_HIP(hipGetLastError());
 
   const size_t cnt_lds = 2 * (MAX_BINS + 1) + 4 * MAX_NB;
@@ -273,21 +391,41 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     LevelIO io;
     io.dst_keys = kdst[L & 1];
     io.dst_vals = vdst[L & 1];
-    hipLaunchKernelGGL((k_fit<KT, 1024>), dim3(cus * 2), dim3(1024), 0, st, p, L, a.trace);
-    hipLaunchKernelGGL((k_count<KT, 512>), dim3(cus * 3), dim3(512), cnt_lds, st, p, L);
-    hipLaunchKernelGGL((k_colscan<256>), dim3(cus * 4), dim3(256), 0, st, p, L);
-    hipLaunchKernelGGL((k_classify<512>), dim3(cus * 2), dim3(512), 0, st, p, L, io);
-    if (small_tile)
-      hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS / 2, PAY>), dim3(g_sc), dim3(SC_NT), sl.total,
-                         st, p, L, io, bins_lds, lay.nbmax);
-    else
-      hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS, PAY>), dim3(g_sc), dim3(SC_NT), sl.total, st,
-                         p, L, io, bins_lds, lay.nbmax);
+    PCF_MARK(PCF_K_FIT, L,
+             hipLaunchKernelGGL((k_fit<KT, 1024>), dim3(cus * 2), dim3(1024), 0, st, p, L,
+                                a.trace));
+    PCF_MARK(PCF_K_COUNT, L,
+             hipLaunchKernelGGL((k_count<KT, 512>), dim3(cus * 3), dim3(512), cnt_lds, st, p, L));
+    PCF_MARK(PCF_K_COLSCAN, L,
+             hipLaunchKernelGGL((k_colscan<256>), dim3(cus * 4), dim3(256), 0, st, p, L));
+    PCF_MARK(PCF_K_CLASSIFY, L,
+             hipLaunchKernelGGL((k_classify<512>), dim3(cus * 2), dim3(512), 0, st, p, L, io));
+    PCF_MARK(PCF_K_SCATTER, L, {
+      if (PAY) {
+        if (sc_ts == SC_TS_PAY)
+          hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS_PAY, 1>), dim3(g_sc), dim3(SC_NT),
+                             sl.total, st, p, L, io, bins_lds, lay.nbmax);
+        else
+          hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS_PAY / 2, 1>), dim3(g_sc), dim3(SC_NT),
+                             sl.total, st, p, L, io, bins_lds, lay.nbmax);
+      } else if (PCF_KEYS_SCATTER == 0) {
+        hipLaunchKernelGGL((k_scatter<KT, SC_NT, 4096, 0>), dim3(g_sc), dim3(SC_NT), sl.total, st,
+                           p, L, io, bins_lds, lay.nbmax);
+      } else {
+        if (sc_ts == 8192)
+          hipLaunchKernelGGL((k_scatter_keys<KT, SC_NT, 8192>), dim3(g_sc), dim3(SC_NT), sl.total,
+                             st, p, L, io, bins_lds, lay.nbmax);
+        else
+          hipLaunchKernelGGL((k_scatter_keys<KT, SC_NT, 4096>), dim3(g_sc), dim3(SC_NT), sl.total,
+                             st, p, L, io, bins_lds, lay.nbmax);
+      }
+    });
     PCF_HIP(hipGetLastError());
     ++levels;
   }
   if (a.levels_run) *a.levels_run = (uint32_t)levels;
   if (a.trace) {
+    t_prof.used = 0;
     // the level's model and bucket sizes for the caller
     Node nd;
     PCF_HIP(hipMemcpyAsync(&nd, p.nodes[0], sizeof(Node), hipMemcpyDeviceToHost, st));
@@ -320,17 +458,29 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     return PCF_OK;
   }
   // finish every small array inside LDS
-  hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), dim3(cus * 4),
-                     dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>), st, p, 0);
-  hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), dim3(cus), dim3(K5_BIG_NT),
-                     sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>), st, p, 1);
+  PCF_MARK(PCF_K_LDS_SMALL, 0,
+           hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), dim3(cus * 4),
+                              dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>), st,
+                              p, 0));
+  PCF_MARK(PCF_K_LDS_BIG, 0, {
+    hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>), dim3(cus * 2),
+                       dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT>), st, p, 1);
+    hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), dim3(cus), dim3(K5_BIG_NT),
+                       sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>), st, p, 2);
+  });
   PCF_HIP(hipGetLastError());
-  if (a.d_status) {
+  if (a.d_status && !t_prof.on) {
     PCF_HIP(hipMemcpyAsync(a.d_status, &p.ctl->status, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     return PCF_OK;
   }
+  if (a.d_status)
+    PCF_HIP(hipMemcpyAsync(a.d_status, &p.ctl->status, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
   PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   PCF_HIP(hipStreamSynchronize(st));
+  {
+    const int r = t_prof.commit(hc, a.n);
+    if (r != PCF_OK) return r;
+  }
   if (hc.status) return hc.status;
   if (hc.overflow) return overflow_status(hc.overflow);
   return PCF_OK;
@@ -356,16 +506,31 @@ static int set_attrs_typed() {
   if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
                      sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>))) != PCF_OK)
     return r;
+  if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
+                     sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT>))) != PCF_OK)
+    return r;
   if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
                      sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>))) != PCF_OK)
     return r;
   const size_t sc_max = 160 * 1024 - 1024;  // scatter launches stay below this
-  if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, SC_TS, PAY>), sc_max)) !=
-      PCF_OK)
-    return r;
-  if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, SC_TS / 2, PAY>),
-                     sc_max)) != PCF_OK)
-    return r;
+  if (PAY) {
+    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, SC_TS_PAY, 1>),
+                       sc_max)) != PCF_OK)
+      return r;
+    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, SC_TS_PAY / 2, 1>),
+                       sc_max)) != PCF_OK)
+      return r;
+  } else {
+    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter_keys<KT, SC_NT, 8192>), sc_max)) !=
+        PCF_OK)
+      return r;
+    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, 4096, 0>), sc_max)) !=
+        PCF_OK)
+      return r;
+    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter_keys<KT, SC_NT, 4096>), sc_max)) !=
+        PCF_OK)
+      return r;
+  }
   return PCF_OK;
 }
 
@@ -448,6 +613,26 @@ size_t pcf_workspace_bytes(int key_type, size_t n, int with_payload, uint32_t nu
   // argsort may need internal keys: include them
   return make_layout(n, with_payload, num_segments ? num_segments : 1, pol, with_payload, 0, 0)
       .total;
+}
+
+int pcf_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return PCF_OK;
+}
+
+int pcf_profile_read(pcf_kernel_stat* out, int reset) {
+  if (!out) return PCF_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (int i = 0; i < PCF_K_COUNT_KINDS; ++i) out[i] = g_prof[i];
+  if (reset) std::memset(g_prof, 0, sizeof(g_prof));
+  return PCF_OK;
+}
+
+const char* pcf_kernel_name(int kind) {
+  static const char* names[PCF_K_COUNT_KINDS] = {"setup", "range", "fit", "count", "colscan",
+                                                 "classify", "scatter", "lds_small", "lds_big"};
+  return (kind >= 0 && kind < PCF_K_COUNT_KINDS) ? names[kind] : "unknown";
 }
 
 int pcf_get_policy(pcf_policy* out) {

@@ -30,7 +30,9 @@ struct LevelIO {
   uint32_t* dst_vals;
 };
 
-// LDS layout of the scatter (bytes), for NW waves and TS keys per tile.
+// LDS layout of the scatter (bytes), for NW waves and TS keys per tile.  The
+// stable variant (with a payload) keeps per-wave bucket counters; the
+// keys-only variant ranks with LDS atomics and needs none.
 struct ScatterLds {
   uint32_t tab, wcnt, runoff, tstart, tcnt, mmlo, mmhi, cmapf, sk, sv, sb, total;
 };
@@ -44,7 +46,7 @@ __host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nb
     return r;
   };
   l.tab = take(2u * (max_bins + 1));
-  l.wcnt = take(2u * nw * nbmax);
+  l.wcnt = take(pay ? 2u * nw * nbmax : 0u);
   l.runoff = take(4u * nbmax);
   l.tstart = take(4u * (nbmax + 1));
   l.tcnt = take(4u * nbmax);
@@ -58,27 +60,49 @@ __host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nb
   return l;
 }
 
+// LDS layout of the keys-only scatter: counters double-buffered across tiles
+// so that a tile needs three barriers.
+struct ScatterKeysLds {
+  uint32_t tab, runoff, tstart, tcnt, mmlo, mmhi, cmapf, sk, sb, total;
+};
+__host__ __device__ inline ScatterKeysLds scatter_keys_lds(uint32_t max_bins, uint32_t nbmax,
+                                                           int ts) {
+  ScatterKeysLds l;
+  uint32_t o = 0;
+  auto take = [&](uint32_t bytes) {
+    uint32_t r = o;
+    o += (bytes + 15u) & ~15u;
+    return r;
+  };
+  l.tab = take(2u * (max_bins + 1));
+  l.runoff = take(2u * 4u * nbmax);
+  l.tstart = take(2u * 4u * (nbmax + 1));
+  l.tcnt = take(2u * 4u * nbmax);
+  l.mmlo = take(8u * nbmax);
+  l.mmhi = take(8u * nbmax);
+  l.cmapf = take(1u * nbmax);
+  l.sk = take(8u * ts);
+  l.sb = take(2u * ts);
+  l.total = o;
+  return l;
+}
+
+// In-LDS finish: arrays of up to CAP keys, one bin per key at every level.
 template <int CAP>
 struct K5Cfg {
-  static constexpr uint32_t BMAX = CAP == 8192 ? 861u : CAP == 4096 ? 512u : CAP == 2048 ? 304u
-                                 : CAP == 1024 ? 181u : 0u;
-  static_assert(BMAX > 0, "unsupported LDS capacity");
-  static constexpr uint32_t SMAX = CAP / 16 + 8;
+  static constexpr uint32_t SMAX = CAP / 16 + 8;  // ranges of >= tau (>= 16) keys
 };
 
 template <int KT, int CAP, int NT>
 struct K5Smem {
-  uint64_t key[CAP];  // key images
-  uint16_t pos[CAP];  // position inside the item
-  uint32_t seg[CAP];  // final segment: start | end << 16
-  uint32_t hist[K5Cfg<CAP>::BMAX + 2];
-  uint32_t cnt[K5Cfg<CAP>::BMAX + 2];
-  uint16_t tab[K5Cfg<CAP>::BMAX + 2];
+  uint64_t key[CAP];      // key images
+  uint16_t pos[CAP];      // position inside the item
+  uint32_t seg[CAP];      // final segment: start | end << 16
+  uint32_t cnt[CAP + 2];  // bin counts, then bin starts
   uint32_t stk[K5Cfg<CAP>::SMAX][3];  // start, end, depth | fail << 31
   uint64_t red64[2 * NT / 64];
   uint32_t red[NT / 64 + 1];
   uint32_t nstk;
-  uint32_t item;
   uint32_t flag;
   uint32_t sh[4];
 };
@@ -95,6 +119,8 @@ template <int NT>
 __global__ void k_classify(Plan p, int L, LevelIO io);
 template <int KT, int NT, int TS, int PAY>
 __global__ void k_scatter(Plan p, int L, LevelIO io, uint32_t max_bins, uint32_t nbmax);
+template <int KT, int NT, int TS>
+__global__ void k_scatter_keys(Plan p, int L, LevelIO io, uint32_t max_bins, uint32_t nbmax);
 template <int KT, int CAP, int NT, int PAY>
 __global__ void k_lds_sort(Plan p, int cls);
 

@@ -9,30 +9,46 @@
 //     b_{i(x)} / alpha, bucket floor(F(x) gamma).
 //
 // One global level is five kernels over a list of nodes (arrays):
-//   k_fit       one workgroup per node: range checks, parameters, alpha
-//               samples histogrammed into beta + 1 bins in LDS, inclusive
-//               prefix sum, bin -> bucket table T (u16) written to HBM;
-//   k_count     per (node, chunk) unit: T in LDS, every key's bucket,
-//               LDS histogram of the gamma + 1 buckets, one column of the
-//               node's bucket-major count matrix;
+//   k_fit       one workgroup per node: range from the producer's partial
+//               minima/maxima, alpha samples histogrammed into beta + 1 bins
+//               in LDS, inclusive prefix sum, bin -> bucket table T (u16);
+//   k_count     per (node, chunk) unit: T in LDS, every key's bucket, LDS
+//               histogram of the gamma + 1 buckets, one column of the node's
+//               bucket-major count matrix;
 //   k_colscan   one wave per (node, bucket): exclusive scan over chunks;
 //   k_classify  one workgroup per node: bucket starts, the paper's per-bucket
-//               decision (recurse / standard sort) and the work lists of the
-//               next level and of the LDS finish;
+//               decision (recurse / standard sort), the next level's nodes
+//               (parameters and arena space reserved once per parent) and the
+//               LDS work items;
 //   k_scatter   per unit: stable tile ranking with wave ballots, LDS staging
-//               in bucket order, coalesced runs to HBM, per-child min/max.
+//               in bucket order, coalesced runs to HBM, per-chunk child ranges.
 // k_lds_sort finishes arrays of at most a few thousand keys inside one
-// workgroup's LDS with the paper's own parameters.
+// workgroup's LDS with the paper's own parameters.  No kernel on the data
+// path uses a same-address global atomic per key or per bucket: those
+// serialize across the chip.
 #include "pcf_kernels.h"
 #include "pcf_block.h"
+
+// Compile-time variants (the defaults are the measured best on MI355X):
+//   PCF_K5_PREFETCH  1: the in-LDS finish loads the next item's keys while it
+//                    sorts the current one.
+#ifndef PCF_K5_PREFETCH
+#define PCF_K5_PREFETCH 0
+#endif
+//   PCF_SC_BATCH_RANK  1: the scatter issues all table reads of a tile's keys
+//                      before their rank atomics.
+//   PCF_SC_BATCH_WRITE 1: the scatter reads all of a thread's staged keys
+//                      before writing any.
+#ifndef PCF_SC_BATCH_RANK
+#define PCF_SC_BATCH_RANK 1
+#endif
+#ifndef PCF_SC_BATCH_WRITE
+#define PCF_SC_BATCH_WRITE 0
+#endif
 
 namespace pcf {
 
 constexpr int ERR_INVALID_KEY = 2;  // PCF_ERR_INVALID_KEY
-
-__device__ __forceinline__ uint64_t load_bits(const void* base, uint64_t i) {
-  return reinterpret_cast<const uint64_t*>(base)[i];
-}
 
 __device__ __forceinline__ bool ctl_ok(const Ctl* c) {
   return *reinterpret_cast<const volatile int32_t*>(&c->status) == 0;
@@ -52,67 +68,147 @@ __global__ void k_init(Plan p) {
   for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
 }
 
-__global__ void k_roots(Plan p, RootArgs a) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.nseg) return;
-  const uint64_t b0 = a.offsets ? a.offsets[s] : 0ull;
-  const uint64_t b1 = a.offsets ? a.offsets[s + 1] : a.n;
-  if (b1 <= b0) return;
-  const uint32_t len = (uint32_t)(b1 - b0);
-  const char* kb = reinterpret_cast<const char*>(a.keys) + b0 * 8ull;
-  const uint32_t* vb = a.vals ? a.vals + b0 : nullptr;
+// Creates the roots: one node (or one LDS item) per non-empty segment.  A
+// single workgroup walks the segments in blocks and hands out indices and
+// arena space with block scans, so no atomics are needed.
+constexpr int ROOT_NT = 1024;
+
+__global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
+  __shared__ uint32_t red[ROOT_NT / 64 + 1];
+  __shared__ unsigned long long base[9];  // nodes, units, table, cm, aux, items 0-2, keys
+  __shared__ uint32_t ush[ROOT_NT], uni[ROOT_NT], unb[ROOT_NT];
   Ctl* c = p.ctl;
-  if (len <= p.pol.lds_cap && !a.force_global) {
-    const int cls = len <= p.pol.small_cap ? 0 : 1;
-    const uint32_t idx = atomicAdd(&c->item_count[cls], 1u);
-    if (idx >= p.cap_items[cls]) {
-      flag_overflow(c);
-      return;
+  if (threadIdx.x < 9) base[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t s0 = 0; s0 < a.nseg; s0 += ROOT_NT) {
+    const uint32_t s = s0 + threadIdx.x;
+    uint32_t len = 0;
+    uint64_t b0 = 0;
+    if (s < a.nseg) {
+      b0 = a.offsets ? a.offsets[s] : 0ull;
+      const uint64_t b1 = a.offsets ? a.offsets[s + 1] : a.n;
+      len = b1 > b0 ? (uint32_t)(b1 - b0) : 0u;
     }
-    Item it;
-    it.src = kb;
-    it.vsrc = vb;
-    it.off = b0;
-    it.rel = 0;
-    it.len = len;
-    it.depth = 0;
-    it.flags = IF_ROOT | (a.iota ? IF_IOTA : 0u);
-    it.seg = s;
-    p.items[cls][idx] = it;
-    return;
+    const bool item = len > 0 && len <= p.pol.lds_cap && !a.force_global;
+    const bool glob = len > 0 && !item;
+    const int icls = item_class(len, p.pol);
+    uint32_t nb = 0, beta = 0, alpha = 0, delta = 0, nch = 0;
+    if (glob) {
+      if (a.fixed_nb) {
+        nb = a.fixed_nb;
+        beta = a.fixed_beta;
+        alpha = a.fixed_alpha;
+        delta = len + 1;
+      } else {
+        node_params(len, NK_PCF, p.pol, nb, beta, alpha, delta);
+      }
+      nch = (len + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
+    }
+    uint32_t tot;
+    const uint32_t o_node = block_excl_scan<ROOT_NT>(glob ? 1u : 0u, red, tot);
+    const uint32_t t_node = tot;
+    const uint32_t o_unit = block_excl_scan<ROOT_NT>(nch, red, tot);
+    const uint32_t t_unit = tot;
+    const uint32_t o_tab = block_excl_scan<ROOT_NT>(glob ? beta + 1 : 0u, red, tot);
+    const uint32_t t_tab = tot;
+    const uint32_t o_cm = block_excl_scan<ROOT_NT>(nch * nb, red, tot);
+    const uint32_t t_cm = tot;
+    const uint32_t o_aux = block_excl_scan<ROOT_NT>(nb, red, tot);
+    const uint32_t t_aux = tot;
+    const uint32_t o_i0 = block_excl_scan<ROOT_NT>(item && icls == 0 ? 1u : 0u, red, tot);
+    const uint32_t t_i0 = tot;
+    const uint32_t o_i1 = block_excl_scan<ROOT_NT>(item && icls == 1 ? 1u : 0u, red, tot);
+    const uint32_t t_i1 = tot;
+    const uint32_t o_i2 = block_excl_scan<ROOT_NT>(item && icls == 2 ? 1u : 0u, red, tot);
+    const uint32_t t_i2 = tot;
+    const char* kb = reinterpret_cast<const char*>(a.keys) + b0 * 8ull;
+    const uint32_t* vb = a.vals ? a.vals + b0 : nullptr;
+    if (item) {
+      const uint64_t idx = base[5 + icls] + (icls == 0 ? o_i0 : (icls == 1 ? o_i1 : o_i2));
+      if (idx < p.cap_items[icls]) {
+        Item it;
+        it.src = kb;
+        it.vsrc = vb;
+        it.off = b0;
+        it.rel = 0;
+        it.len = len;
+        it.depth = 0;
+        it.flags = IF_ROOT | (a.iota ? IF_IOTA : 0u);
+        it.seg = s;
+        p.items[icls][idx] = it;
+      } else {
+        flag_overflow(c);
+      }
+    }
+    bool glob_ok = true;
+    if (glob) {
+      const uint64_t ni = base[0] + o_node, ub = base[1] + o_unit, tb = base[2] + o_tab;
+      const uint64_t cb = base[3] + o_cm, ab = base[4] + o_aux;
+      if (ni < p.cap_nodes && ub + nch <= p.cap_units && tb + beta + 1 <= p.cap_table &&
+          cb + (uint64_t)nch * nb <= p.cap_cm && ab + nb <= p.cap_aux) {
+        Node nd = {};
+        nd.src = kb;
+        nd.vsrc = vb;
+        nd.mmp = p.mmr + ub;
+        nd.off = b0;
+        nd.rel = 0;
+        nd.seed = a.has_fixed_seed ? a.fixed_seed : node_seed(p.seed, s, 0, 0);
+        nd.table_off = tb;
+        nd.cm_off = cb;
+        nd.len = len;
+        nd.seg = s;
+        nd.depth = 0;
+        nd.kind = NK_PCF;
+        nd.nchunks = nch;
+        nd.unit_base = (uint32_t)ub;
+        nd.aux_off = (uint32_t)ab;
+        nd.mmn = nch;
+        nd.nb = nb;
+        nd.nbits = bits_for(nb);
+        nd.beta = beta;
+        nd.alpha = alpha;
+        nd.delta = delta;
+        nd.iota = a.iota;
+        p.nodes[0][ni] = nd;
+      } else {
+        flag_overflow(c);
+        glob_ok = false;
+      }
+    }
+    // unit records of this block's roots, written by the whole workgroup
+    ush[threadIdx.x] = (glob && glob_ok) ? nch : 0u;
+    uni[threadIdx.x] = (uint32_t)(base[0] + o_node);
+    unb[threadIdx.x] = (uint32_t)(base[1] + o_unit);
+    __syncthreads();
+    for (uint32_t j = 0; j < ROOT_NT; ++j) {
+      const uint32_t cnt = ush[j];
+      for (uint32_t i = threadIdx.x; i < cnt; i += ROOT_NT) p.units[0][unb[j] + i] = Unit{uni[j], i};
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      base[0] += t_node;
+      base[1] += t_unit;
+      base[2] += t_tab;
+      base[3] += t_cm;
+      base[4] += t_aux;
+      base[5] += t_i0;
+      base[6] += t_i1;
+      base[7] += t_i2;
+    }
+    if (glob) atomicAdd(&base[8], (unsigned long long)len);
+    __syncthreads();
   }
-  const uint32_t ni = atomicAdd(&c->lv[0].num_nodes, 1u);
-  if (ni >= p.cap_nodes) {
-    flag_overflow(c);
-    return;
+  if (threadIdx.x == 0) {
+    c->lv[0].num_nodes = (uint32_t)base[0];
+    c->lv[0].num_units = (uint32_t)base[1];
+    c->lv[0].table_used = base[2];
+    c->lv[0].cm_used = base[3];
+    c->lv[0].aux_used = (uint32_t)base[4];
+    c->item_count[0] = (uint32_t)base[5];
+    c->item_count[1] = (uint32_t)base[6];
+    c->item_count[2] = (uint32_t)base[7];
+    c->lv[0].keys = base[8];
   }
-  const uint32_t nch = (len + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
-  const uint32_t ub = atomicAdd(&c->lv[0].num_units, nch);
-  if (ub + nch > p.cap_units) {
-    flag_overflow(c);
-    return;
-  }
-  for (uint32_t i = 0; i < nch; ++i) p.units[0][ub + i] = Unit{ni, i};
-  Node nd = {};
-  nd.src = kb;
-  nd.vsrc = vb;
-  nd.off = b0;
-  nd.rel = 0;
-  nd.seed = a.has_fixed_seed ? a.fixed_seed : node_seed(p.seed, s, 0, 0);
-  nd.min_img = ~0ull;
-  nd.max_img = 0ull;
-  nd.len = len;
-  nd.seg = s;
-  nd.depth = 0;
-  nd.kind = NK_PCF;
-  nd.nchunks = nch;
-  nd.unit_base = ub;
-  nd.fixed = a.fixed_nb ? 1u : 0u;
-  nd.alpha = a.fixed_alpha;
-  nd.beta = a.fixed_beta;
-  nd.nb = a.fixed_nb;
-  nd.iota = a.iota;
-  p.nodes[0][ni] = nd;
 }
 
 // Chunk [b, e) of a unit: the node's keys split into nchunks equal parts.
@@ -125,25 +221,39 @@ __device__ __forceinline__ void chunk_range(const Node& nd, uint32_t chunk, uint
 // ---------------------------------------------------------------------------
 // K0: range of the level-0 nodes (x_min, x_max of Sec. 3.3) + key validation
 // ---------------------------------------------------------------------------
+// Each unit writes its own partial minimum and maximum; the fit kernel
+// reduces them (no atomics on the node).
 template <int KT, int NT>
 __global__ __launch_bounds__(NT) void k_range(Plan p) {
   __shared__ uint64_t red[2 * NT / 64];
   __shared__ uint32_t bad_sh;
   const uint32_t nu = p.ctl->lv[0].num_units;
+  constexpr int U = 8;
   for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
     const Unit un = p.units[0][u];
-    Node& nd = p.nodes[0][un.node];
+    const Node& nd = p.nodes[0][un.node];
     uint32_t b, e;
     chunk_range(nd, un.chunk, b, e);
     const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
     uint64_t lo = ~0ull, hi = 0ull;
     bool bad = false;
-    for (uint32_t i = b + threadIdx.x; i < e; i += NT) {
-      const uint64_t bits = __builtin_nontemporal_load(src + i);
-      if (KT == KT_F64) bad |= !f64_bits_valid(bits);
-      const uint64_t im = img_of<KT>(bits);
-      lo = im < lo ? im : lo;
-      hi = im > hi ? im : hi;
+    for (uint32_t base = b; base < e; base += U * NT) {
+      uint64_t v[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const uint32_t i = base + k * NT + threadIdx.x;
+        v[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const uint32_t i = base + k * NT + threadIdx.x;
+        if (i < e) {
+          if (KT == KT_F64) bad |= !f64_bits_valid(v[k]);
+          const uint64_t im = img_of<KT>(v[k]);
+          lo = im < lo ? im : lo;
+          hi = im > hi ? im : hi;
+        }
+      }
     }
     if (threadIdx.x == 0) bad_sh = 0;
     __syncthreads();
@@ -151,94 +261,57 @@ __global__ __launch_bounds__(NT) void k_range(Plan p) {
     block_minmax_u64<NT>(lo, hi, red);
     if (threadIdx.x == 0) {
       if (bad_sh) atomicMax(&p.ctl->status, ERR_INVALID_KEY);
-      atomicMin(&nd.min_img, (unsigned long long)lo);
-      atomicMax(&nd.max_img, (unsigned long long)hi);
+      p.mmr[u] = MinMax{lo, hi};
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// K1: fit -- sample, histogram, prefix sum, bin -> bucket table
+// K1: fit -- range, sample, histogram, prefix sum, bin -> bucket table
 // ---------------------------------------------------------------------------
 template <int KT, int NT>
 __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
   __shared__ uint32_t hist[MAX_BINS + 1];
   __shared__ uint32_t red[NT / 64 + 1];
-  __shared__ uint64_t alloc_sh[4];
-  __shared__ uint32_t ok_sh;
+  __shared__ uint64_t red64[2 * NT / 64];
   const int s = L & 1;
   Ctl* c = p.ctl;
-  LevelCtr& lc = c->lv[L];
-  const uint32_t nn = lc.num_nodes;
+  const uint32_t nn = c->lv[L].num_nodes;
+  if (!ctl_ok(c)) return;  // status is fixed while this kernel runs
   for (uint32_t ni = blockIdx.x; ni < nn; ni += gridDim.x) {
-    if (!ctl_ok(c)) return;
     Node& nd = p.nodes[s][ni];
-    const uint64_t lo = nd.min_img, hi = nd.max_img;
+    // units and tasks of the node (also for a single-valued node: its units copy it)
+    for (uint32_t i = threadIdx.x; i < nd.nchunks; i += NT)
+      p.units[s][nd.unit_base + i] = Unit{ni, i};
+    for (uint32_t q = threadIdx.x; q < nd.nb; q += NT) p.task_node[s][nd.aux_off + q] = ni;
+    // range: reduce the producer's partial minima / maxima
+    uint64_t lo = ~0ull, hi = 0ull;
+    for (uint32_t i = threadIdx.x; i < nd.mmn; i += NT) {
+      const MinMax m = nd.mmp[i];
+      lo = m.lo < lo ? m.lo : lo;
+      hi = m.hi > hi ? m.hi : hi;
+    }
+    block_minmax_u64<NT>(lo, hi, red64);
     if (lo == hi) {
       if (threadIdx.x == 0) {
+        nd.min_img = lo;
+        nd.max_img = hi;
         nd.state = NS_DONE;
-        atomicAdd(&c->n_done_nodes, 1u);
       }
+      __syncthreads();
       continue;
     }
-    uint32_t kind = nd.kind, nb, nbits, beta = 0, alpha = 0, delta, shift = 0;
+    uint32_t kind = nd.kind, shift = 0;
+    const uint32_t nb = nd.nb, beta = nd.beta, alpha = nd.alpha;
     BinFn f = {};
-    if (kind == NK_PCF) {
-      if (nd.fixed) {
-        nb = nd.nb;
-        beta = nd.beta;
-        alpha = nd.alpha;
-        delta = nd.len + 1;
-      } else {
-        const uint32_t tgt = (nd.len + p.pol.target_child - 1) / p.pol.target_child;
-        nb = 2;
-        while (nb < tgt && nb < p.pol.max_buckets) nb <<= 1;
-        beta = p.pol.bins_per_bucket * nb;
-        if (beta > p.pol.max_bins) beta = p.pol.max_bins;
-        alpha = p.pol.samples_per_bucket * nb;
-        if (alpha > p.pol.max_samples) alpha = p.pol.max_samples;
-        delta = root34(nd.len);
-      }
-      if (!bin_setup<KT>(f, lo, hi, beta)) {
-        kind = NK_RADIX;  // scale not finite: a bucketing failure
-        if (threadIdx.x == 0) atomicAdd(&c->n_radix_nodes, 1u);
-      }
-    }
+    if (kind == NK_PCF && !bin_setup<KT>(f, lo, hi, beta)) kind = NK_RADIX;  // scale not finite
     if (kind == NK_RADIX) {
+      // standard sort by most-significant digits of the range: nb buckets
       const uint64_t range = hi - lo;
       const uint32_t top = 63u - (uint32_t)__clzll((long long)range);
-      shift = top >= 7 ? top - 7 : 0u;
-      nb = RADIX_NB;
-      delta = 0xffffffffu;
-    }
-    nbits = 32u - (uint32_t)__clz((int)(nb - 1));
-    if (nb == 1) nbits = 0;
-    // allocate the node's share of the level arenas
-    if (threadIdx.x == 0) {
-      const uint64_t tsz = kind == NK_PCF ? (uint64_t)beta + 1 : 0;
-      const uint64_t t0 = atomicAdd(&lc.table_used, (unsigned long long)tsz);
-      const uint64_t msz = (uint64_t)nd.nchunks * nb;
-      const uint64_t m0 = atomicAdd(&lc.cm_used, (unsigned long long)msz);
-      const uint32_t a0 = atomicAdd(&lc.aux_used, nb);
-      const uint32_t k0 = atomicAdd(&lc.tasks, nb);
-      uint32_t ok = 1;
-      if (t0 + tsz > p.cap_table || m0 + msz > p.cap_cm || a0 + nb > p.cap_aux ||
-          k0 + nb > p.cap_tasks) {
-        flag_overflow(c);
-        ok = 0;
-      }
-      alloc_sh[0] = t0;
-      alloc_sh[1] = m0;
-      alloc_sh[2] = a0;
-      alloc_sh[3] = k0;
-      ok_sh = ok;
-    }
-    __syncthreads();
-    if (!ok_sh) return;
-    const uint64_t t0 = alloc_sh[0], m0 = alloc_sh[1];
-    const uint32_t a0 = (uint32_t)alloc_sh[2], k0 = (uint32_t)alloc_sh[3];
-    for (uint32_t b = threadIdx.x; b < nb; b += NT) p.task_node[s][k0 + b] = ni;
-    if (kind == NK_PCF) {
+      const uint32_t nbits = nd.nbits;
+      shift = top + 1 > nbits ? top + 1 - nbits : 0u;
+    } else {
       for (uint32_t i = threadIdx.x; i <= beta; i += NT) hist[i] = 0u;
       __syncthreads();
       const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
@@ -251,31 +324,26 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       if (trace && L == 0 && ni == 0 && p.trace_b)
         for (uint32_t i = threadIdx.x; i <= beta; i += NT) p.trace_b[i] = hist[i];
       const uint32_t gamma = nb - 1;
-      uint16_t* tab = p.table[s] + t0;
+      uint16_t* tab = p.table[s] + nd.table_off;
       for (uint32_t i = threadIdx.x; i <= beta; i += NT)
         tab[i] = (uint16_t)(((uint64_t)hist[i] * gamma) / alpha);
     }
     if (threadIdx.x == 0) {
       nd.kind = kind;
       nd.state = NS_ACTIVE;
-      nd.nb = nb;
-      nd.nbits = nbits;
-      nd.beta = beta;
-      nd.alpha = alpha;
-      nd.delta = delta;
       nd.shift = shift;
       nd.halves = f.halves;
       nd.scale = f.s;
-      nd.table_off = t0;
-      nd.cm_off = m0;
-      nd.aux_off = a0;
-      nd.task_base = k0;
+      nd.min_img = lo;
+      nd.max_img = hi;
     }
     __syncthreads();
   }
 }
 
-// Bucket of a key in an active node.
+// Bucket of a key in an active node.  index() is pure arithmetic (the bin,
+// or the radix digit); finish() maps a bin through the LDS table, so callers
+// can batch the table reads of many keys.
 template <int KT>
 struct Bucketer {
   BinFn f;
@@ -283,9 +351,15 @@ struct Bucketer {
   uint32_t shift;
   uint32_t radix;
   const uint16_t* tab;  // LDS copy of T
-  __device__ __forceinline__ uint32_t operator()(uint64_t bits) const {
+  __device__ __forceinline__ uint32_t index(uint64_t bits) const {
     if (radix) return (uint32_t)((img_of<KT>(bits) - lo_img) >> shift);
-    return tab[bin_of<KT>(f, bits)];
+    return bin_of<KT>(f, bits);
+  }
+  __device__ __forceinline__ uint32_t finish(uint32_t idx) const {
+    return radix ? idx : (uint32_t)tab[idx];
+  }
+  __device__ __forceinline__ uint32_t operator()(uint64_t bits) const {
+    return finish(index(bits));
   }
 };
 
@@ -317,13 +391,14 @@ __device__ __forceinline__ Bucketer<KT> make_bucketer(const Node& nd, const uint
 template <int KT, int NT>
 __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
   extern __shared__ __align__(16) unsigned char lds[];
-  uint16_t* tab = reinterpret_cast<uint16_t*>(lds);                    // MAX_BINS + 1
+  uint16_t* tab = reinterpret_cast<uint16_t*>(lds);                       // MAX_BINS + 1
   uint32_t* hist = reinterpret_cast<uint32_t*>(lds + 2 * (MAX_BINS + 1));  // MAX_NB
   const int s = L & 1;
   Ctl* c = p.ctl;
   const uint32_t nu = c->lv[L].num_units;
+  if (!ctl_ok(c)) return;
+  const int l = lane_id();
   for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
-    if (!ctl_ok(c)) return;
     const Unit un = p.units[s][u];
     const Node& nd = p.nodes[s][un.node];
     if (nd.state != NS_ACTIVE) continue;
@@ -336,31 +411,47 @@ __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
     uint32_t b, e;
     chunk_range(nd, un.chunk, b, e);
     const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
-    constexpr int U = 4;
-    const int l = lane_id();
-    for (uint32_t base = b; base < e; base += U * NT) {
-      uint64_t v[U];
+    // software pipeline: the next block's keys are loaded while this one is
+    // counted; table reads and LDS atomics of a block are issued back to back
+    constexpr int U = 8;
+    uint64_t v[U], nv[U];
 #pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const uint32_t i = base + k * NT + threadIdx.x;
-        v[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+    for (int k = 0; k < U; ++k) {
+      const uint32_t i = b + k * NT + threadIdx.x;
+      nv[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+    }
+    for (uint32_t base = b; base < e; base += U * NT) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) v[k] = nv[k];
+      const uint32_t nb2 = base + U * NT;
+      if (nb2 < e) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const uint32_t i = nb2 + k * NT + threadIdx.x;
+          nv[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+        }
       }
+      uint32_t q[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) q[k] = bk.index(v[k]);
+#pragma unroll
+      for (int k = 0; k < U; ++k) q[k] = bk.finish(q[k]);
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const uint32_t i = base + k * NT + threadIdx.x;
         const bool valid = i < e;
-        uint32_t q = valid ? bk(v[k]) : 0u;
-        if (q >= nb) {
+        uint32_t qk = valid ? q[k] : 0u;
+        if (qk >= nb) {
           flag_internal(c);
-          q = nb - 1;
+          qk = nb - 1;
         }
         // a whole wave in one bucket (runs of duplicates): one add
-        const uint32_t q0 = __shfl(q, 0, 64);
+        const uint32_t q0 = __builtin_amdgcn_readfirstlane(qk);
         const uint64_t act = __ballot(valid);
-        if (act == ~0ull && __all(q == q0)) {
+        if (act == ~0ull && __all(qk == q0)) {
           if (l == 0) atomicAdd(&hist[q0], 64u);
         } else if (valid) {
-          atomicAdd(&hist[q], 1u);
+          atomicAdd(&hist[qk], 1u);
         }
       }
     }
@@ -378,14 +469,15 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_colscan(Plan p, int L) {
   const int s = L & 1;
   Ctl* c = p.ctl;
-  const uint32_t nt = c->lv[L].tasks;
+  const uint32_t nt = c->lv[L].aux_used;
+  if (!ctl_ok(c)) return;
   constexpr int NW = NT / 64;
   const int l = lane_id();
   for (uint32_t t = blockIdx.x * NW + wave_id(); t < nt; t += gridDim.x * NW) {
-    if (!ctl_ok(c)) return;
     const uint32_t ni = p.task_node[s][t];
     const Node& nd = p.nodes[s][ni];
-    const uint32_t q = t - nd.task_base;
+    if (nd.state != NS_ACTIVE) continue;
+    const uint32_t q = t - nd.aux_off;
     const uint32_t C = nd.nchunks;
     uint32_t* col = p.cm[s] + nd.cm_off + (uint64_t)q * C;
     uint32_t carry = 0;
@@ -404,8 +496,6 @@ __global__ __launch_bounds__(NT) void k_colscan(Plan p, int L) {
 // ---------------------------------------------------------------------------
 enum : uint32_t { BC_EMPTY = 0, BC_LDS_PCF = 1, BC_LDS_STD = 2, BC_GLB_PCF = 3, BC_GLB_RADIX = 4 };
 
-
-
 template <int NT>
 __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
   __shared__ uint32_t st[MAX_NB + 1];
@@ -413,13 +503,16 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
   __shared__ uint8_t cls[MAX_NB];
   __shared__ uint8_t istart[MAX_NB];
   __shared__ uint32_t red[NT / 64 + 1];
+  __shared__ unsigned long long base[8];
   const int s = L & 1, s1 = (L + 1) & 1;
   Ctl* c = p.ctl;
   const uint32_t nn = c->lv[L].num_nodes;
+  if (!ctl_ok(c)) return;
   const uint32_t cap = p.pol.lds_cap;
   const uint32_t half = p.pol.small_cap / 2 ? p.pol.small_cap / 2 : 1;
+  const bool has_next = L + 1 < MAX_LEVELS;
+  LevelCtr* ln = &c->lv[has_next ? L + 1 : L];
   for (uint32_t ni = blockIdx.x; ni < nn; ni += gridDim.x) {
-    if (!ctl_ok(c)) return;
     const Node& nd = p.nodes[s][ni];
     if (nd.state != NS_ACTIVE) continue;
     const uint32_t nb = nd.nb;
@@ -453,9 +546,8 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
     // sorted buckets, because bucket ranges are disjoint and ordered).
     for (uint32_t q = threadIdx.x; q < nb; q += NT) {
       const uint32_t k = cls[q];
-      const bool lds = k <= BC_LDS_STD;
       uint32_t start = 0;
-      if (lds) {
+      if (k <= BC_LDS_STD) {
         const uint32_t g = k == BC_EMPTY ? lds_grp : k;
         const uint32_t sz = st[q + 1] - st[q];
         if (q == 0) {
@@ -471,79 +563,162 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
       istart[q] = (uint8_t)start;
     }
     __syncthreads();
-    LevelCtr* ln = &c->lv[L + 1 < MAX_LEVELS ? L + 1 : MAX_LEVELS - 1];
-    for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-      const uint32_t k = cls[q];
-      cmap[q] = -1;
-      if (istart[q]) {
-        uint32_t e = q + 1;
-        while (e < nb && cls[e] <= BC_LDS_STD && !istart[e]) ++e;
-        const uint32_t ilen = st[e] - st[q];
-        if (ilen > 0) {
-          const uint32_t g = k == BC_EMPTY ? lds_grp : k;
-          const int ic = ilen <= p.pol.small_cap ? 0 : 1;
-          const uint32_t idx = atomicAdd(&c->item_count[ic], 1u);
-          if (idx >= p.cap_items[ic]) {
-            flag_overflow(c);
-          } else {
-            Item it;
-            const uint64_t off = nd.off + st[q];
-            it.src = reinterpret_cast<const char*>(io.dst_keys) + off * 8ull;
-            it.vsrc = p.has_pay ? io.dst_vals + off : nullptr;
-            it.off = off;
-            it.rel = nd.rel + st[q];
-            it.len = ilen;
-            it.depth = nd.depth + 1;
-            it.flags = g == BC_LDS_STD ? IF_STD : 0u;
-            it.seg = nd.seg;
-            p.items[ic][idx] = it;
-            if (g == BC_LDS_STD) atomicAdd(&c->n_fail_items, 1u);
+    // per bucket: item length (0 if none) and the child's arena needs; the
+    // LDS arrays are reused for the scans (pre: item class 0, st kept)
+    constexpr int PER = (MAX_NB + NT - 1) / NT;
+    uint32_t ilen[PER], icl[PER];
+    uint32_t cnb[PER], cbeta[PER], calpha[PER], cdelta[PER], cnch[PER];
+    uint32_t n_i0 = 0, n_i1 = 0, n_i2 = 0, n_node = 0, n_unit = 0, n_tab = 0, n_cm = 0, n_aux = 0, n_key = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const uint32_t q = threadIdx.x * PER + k;  // contiguous runs per thread
+      ilen[k] = 0;
+      icl[k] = 0;
+      cnb[k] = 0;
+      cnch[k] = 0;
+      cbeta[k] = 0;
+      if (q < nb) {
+        const uint32_t kq = cls[q];
+        if (istart[q]) {
+          uint32_t e = q + 1;
+          while (e < nb && cls[e] <= BC_LDS_STD && !istart[e]) ++e;
+          ilen[k] = st[e] - st[q];
+          icl[k] = (uint32_t)item_class(ilen[k], p.pol);
+          if (ilen[k]) {
+            if (icl[k] == 0) ++n_i0;
+            else if (icl[k] == 1) ++n_i1;
+            else ++n_i2;
           }
         }
+        if (kq >= BC_GLB_PCF && has_next) {
+          const uint32_t sz = st[q + 1] - st[q];
+          node_params(sz, kq == BC_GLB_RADIX ? NK_RADIX : NK_PCF, p.pol, cnb[k], cbeta[k],
+                      calpha[k], cdelta[k]);
+          cnch[k] = (sz + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
+          ++n_node;
+          n_unit += cnch[k];
+          n_tab += kq == BC_GLB_PCF ? cbeta[k] + 1 : 0u;
+          n_cm += cnch[k] * cnb[k];
+          n_aux += cnb[k];
+          n_key += sz;
+        }
       }
-      if (k >= BC_GLB_PCF) {
+    }
+    uint32_t t0, t1, t2, t3, t4, t5, t6, t7;
+    const uint32_t o_i0 = block_excl_scan<NT>(n_i0, red, t0);
+    const uint32_t o_i1 = block_excl_scan<NT>(n_i1, red, t1);
+    const uint32_t o_i2 = block_excl_scan<NT>(n_i2, red, t7);
+    const uint32_t o_node = block_excl_scan<NT>(n_node, red, t2);
+    const uint32_t o_unit = block_excl_scan<NT>(n_unit, red, t3);
+    const uint32_t o_tab = block_excl_scan<NT>(n_tab, red, t4);
+    const uint32_t o_cm = block_excl_scan<NT>(n_cm, red, t5);
+    const uint32_t o_aux = block_excl_scan<NT>(n_aux, red, t6);
+    uint32_t tk;
+    block_excl_scan<NT>(n_key, red, tk);
+    if (threadIdx.x == 0) {
+      // one reservation per parent node and list
+      base[0] = t0 ? atomicAdd(&c->item_count[0], t0) : 0u;
+      base[1] = t1 ? atomicAdd(&c->item_count[1], t1) : 0u;
+      base[7] = t7 ? atomicAdd(&c->item_count[2], t7) : 0u;
+      base[2] = t2 ? atomicAdd(&ln->num_nodes, t2) : 0u;
+      base[3] = t3 ? atomicAdd(&ln->num_units, t3) : 0u;
+      base[4] = t4 ? atomicAdd(&ln->table_used, (unsigned long long)t4) : 0ull;
+      base[5] = t5 ? atomicAdd(&ln->cm_used, (unsigned long long)t5) : 0ull;
+      base[6] = t6 ? atomicAdd(&ln->aux_used, t6) : 0u;
+      if (tk) atomicAdd(&ln->keys, (unsigned long long)tk);
+    }
+    __syncthreads();
+    uint64_t bi0 = base[0] + o_i0, bi1 = base[1] + o_i1, bi2 = base[7] + o_i2,
+             bn = base[2] + o_node,
+             bu = base[3] + o_unit, bt = base[4] + o_tab, bc = base[5] + o_cm,
+             ba = base[6] + o_aux;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const uint32_t q = threadIdx.x * PER + k;
+      if (q >= nb) break;
+      cmap[q] = -1;
+      if (ilen[k]) {
+        const int ic = (int)icl[k];
+        const uint64_t idx = ic == 0 ? bi0++ : (ic == 1 ? bi1++ : bi2++);
+        if (idx >= p.cap_items[ic]) {
+          flag_overflow(c);
+        } else {
+          const uint32_t kq = cls[q];
+          const uint32_t g = kq == BC_EMPTY ? lds_grp : kq;
+          Item it;
+          const uint64_t off = nd.off + st[q];
+          it.src = reinterpret_cast<const char*>(io.dst_keys) + off * 8ull;
+          it.vsrc = p.has_pay ? io.dst_vals + off : nullptr;
+          it.off = off;
+          it.rel = nd.rel + st[q];
+          it.len = ilen[k];
+          it.depth = nd.depth + 1;
+          it.flags = g == BC_LDS_STD ? IF_STD : 0u;
+          it.seg = nd.seg;
+          p.items[ic][idx] = it;
+        }
+      }
+      if (cnb[k]) {
+        const uint32_t kq = cls[q];
         const uint32_t sz = st[q + 1] - st[q];
-        if (L + 1 >= MAX_LEVELS) {
+        const uint64_t ci = bn++, ub = bu, tb = bt, cb = bc, ab = ba;
+        const bool radix = kq == BC_GLB_RADIX;
+        bu += cnch[k];
+        bt += radix ? 0u : cbeta[k] + 1;
+        bc += (uint64_t)cnch[k] * cnb[k];
+        ba += cnb[k];
+        if (ci >= p.cap_nodes || ub + cnch[k] > p.cap_units || tb + cbeta[k] + 1 > p.cap_table ||
+            cb + (uint64_t)cnch[k] * cnb[k] > p.cap_cm || ab + cnb[k] > p.cap_aux) {
           flag_overflow(c);
           continue;
         }
-        const uint32_t ci = atomicAdd(&ln->num_nodes, 1u);
-        const uint32_t nch = (sz + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
-        const uint32_t ub = atomicAdd(&ln->num_units, nch);
-        if (ci >= p.cap_nodes || ub + nch > p.cap_units) {
-          flag_overflow(c);
-          continue;
-        }
-        for (uint32_t i = 0; i < nch; ++i) p.units[s1][ub + i] = Unit{ci, i};
         Node ch = {};
         const uint64_t off = nd.off + st[q];
         ch.src = reinterpret_cast<const char*>(io.dst_keys) + off * 8ull;
         ch.vsrc = p.has_pay ? io.dst_vals + off : nullptr;
+        ch.mmp = p.mm[s] + nd.cm_off + (uint64_t)q * nd.nchunks;  // filled by the scatter
+        ch.mmn = nd.nchunks;
         ch.off = off;
         ch.rel = nd.rel + st[q];
         ch.seed = node_seed(p.seed, nd.seg, nd.depth + 1, ch.rel);
-        ch.min_img = ~0ull;
-        ch.max_img = 0ull;
+        ch.table_off = tb;
+        ch.cm_off = cb;
         ch.len = sz;
         ch.seg = nd.seg;
         ch.depth = nd.depth + 1;
-        ch.kind = k == BC_GLB_RADIX ? NK_RADIX : NK_PCF;
-        ch.nchunks = nch;
-        ch.unit_base = ub;
+        ch.kind = radix ? NK_RADIX : NK_PCF;
+        ch.nchunks = cnch[k];
+        ch.unit_base = (uint32_t)ub;
+        ch.aux_off = (uint32_t)ab;
+        ch.nb = cnb[k];
+        ch.nbits = bits_for(cnb[k]);
+        ch.beta = cbeta[k];
+        ch.alpha = calpha[k];
+        ch.delta = cdelta[k];
         p.nodes[s1][ci] = ch;
         cmap[q] = (int32_t)ci;
-        if (k == BC_GLB_RADIX) atomicAdd(&c->n_radix_nodes, 1u);
       }
+    }
+    if (!has_next) {
+      for (uint32_t q = threadIdx.x; q < nb; q += NT)
+        if (cls[q] >= BC_GLB_PCF) flag_overflow(c);
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// K4: scatter -- stable, LDS-staged, coalesced
+// K4: scatter -- LDS-staged, coalesced; stable when a payload travels
 // ---------------------------------------------------------------------------
+// With a payload the tile ranking is stable (wave ballots + per-wave bucket
+// counters) so that equal keys keep their input order.  Keys alone need no
+// stability (equal keys are the same bits), so their tile ranks come from LDS
+// atomics, which is several times cheaper.
+// The second launch bound is waves per SIMD: 4 keeps two 512-thread
+// workgroups resident per CU (at most 128 VGPRs); the stable variant needs
+// more registers and runs one workgroup per CU.
 template <int KT, int NT, int TS, int PAY>
-__global__ __launch_bounds__(NT) void k_scatter(Plan p, int L, LevelIO io, uint32_t max_bins,
+__global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, LevelIO io, uint32_t max_bins,
                                                 uint32_t nbmax) {
   constexpr int NW = NT / 64;
   constexpr int PW = TS / NW;   // keys of a wave per tile
@@ -564,16 +739,16 @@ __global__ __launch_bounds__(NT) void k_scatter(Plan p, int L, LevelIO io, uint3
   uint16_t* sb = reinterpret_cast<uint16_t*>(lds + lay.sb);
   __shared__ uint32_t red[NW + 1];
 
-  const int s = L & 1, s1 = (L + 1) & 1;
+  const int s = L & 1;
   Ctl* c = p.ctl;
   const uint32_t nu = c->lv[L].num_units;
+  if (!ctl_ok(c)) return;
   const int l = lane_id(), w = wave_id();
   uint64_t* dk = reinterpret_cast<uint64_t*>(io.dst_keys);
   uint32_t* dv = io.dst_vals;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
 
   for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
-    if (!ctl_ok(c)) return;
     const Unit un = p.units[s][u];
     const Node& nd = p.nodes[s][un.node];
     uint32_t cb, ce;
@@ -605,66 +780,128 @@ __global__ __launch_bounds__(NT) void k_scatter(Plan p, int L, LevelIO io, uint3
       cmapf[q] = cm[q] >= 0 ? 1 : 0;
       mmlo[q] = ~0ull;
       mmhi[q] = 0ull;
+      tcnt[q] = 0u;
     }
-    for (uint32_t q = threadIdx.x; q < NW * nb; q += NT) wcnt[q] = 0;
-    __syncthreads();
+    if (PAY)
+      for (uint32_t q = threadIdx.x; q < NW * nb; q += NT) wcnt[q] = 0;
+    bool glb = false;
+    for (uint32_t q = threadIdx.x; q < nb; q += NT) glb |= cm[q] >= 0;
+    const bool any_glb = __syncthreads_or(glb) != 0;
     const Bucketer<KT> bk = make_bucketer<KT>(nd, tab);
     const uint32_t* vsrc = nd.vsrc;
     const bool iota = PAY && vsrc == nullptr;
 
+    // software pipeline: the next tile's keys are in flight while this one
+    // is ranked, staged and written
+    uint64_t key[R], nkey[R];
+    uint32_t val[R], nval[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = w * PW + r * 64 + l;
+      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(src + cb + i) : 0ull;
+      if (PAY) nval[r] = cb + i < ce ? (iota ? (uint32_t)nd.rel + cb + i : vsrc[cb + i]) : 0u;
+    }
     for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
       const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
-      // 1. load: wave w owns keys [w*PW, (w+1)*PW) of the tile, round r lane l
-      uint64_t key[R];
-      uint32_t val[R];
-      uint32_t code[R];  // bucket << 16 | rank inside the wave's part
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        key[r] = i < tn ? __builtin_nontemporal_load(src + t0 + i) : 0ull;
-        if (PAY) val[r] = i < tn ? (iota ? (uint32_t)nd.rel + t0 + i : vsrc[t0 + i]) : 0u;
+        key[r] = nkey[r];
+        if (PAY) val[r] = nval[r];
       }
-      // 2. bucket + stable rank inside the wave (ballot match per round)
+      const uint32_t t1 = t0 + TS;
+      if (t1 < ce) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(src + t1 + i) : 0ull;
+          if (PAY) nval[r] = t1 + i < ce ? (iota ? (uint32_t)nd.rel + t1 + i : vsrc[t1 + i]) : 0u;
+        }
+      }
+      // bucket and rank of every key of the tile; wave w owns keys
+      // [w*PW, (w+1)*PW), round r lane l
+      uint32_t code[R];  // bucket << 16 | rank
       uint16_t* wc = wcnt + w * nb;
+      uint32_t qq[R];
+      if (PCF_SC_BATCH_RANK) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
-        const bool valid = i < tn;
-        uint32_t q = valid ? bk(key[r]) : 0u;
+        uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish(qq[r]) : bk(key[r])) : 0u;
         if (q >= nb) {  // range check: cannot happen for a consistent model
           flag_internal(c);
           q = nb - 1;
         }
-        const uint64_t act = __ballot(valid);
-        const uint64_t peers = wave_match(q, nbits, act);
-        const uint32_t rk = (uint32_t)__popcll(peers & lanemask_lt());
-        uint32_t base = 0;
-        if (valid) base = wc[q];
-        if (valid && rk == 0) wc[q] = (uint16_t)(base + (uint32_t)__popcll(peers));
-        code[r] = (q << 16) | (base + rk);
+        qq[r] = q;
+      }
+      if (any_glb) {
+        // child ranges (lanes here hold unrelated buckets: few LDS conflicts)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          if (i < tn && cmapf[qq[r]]) {
+            const unsigned long long im = img_of<KT>(key[r]);
+            atomicMin(&mmlo[qq[r]], im);
+            atomicMax(&mmhi[qq[r]], im);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = w * PW + r * 64 + l;
+        const bool valid = i < tn;
+        const uint32_t q = qq[r];
+        if (PAY) {
+          // stable: rank among equal buckets in lane order, per-wave counters
+          const uint64_t act = __ballot(valid);
+          const uint64_t peers = wave_match(q, nbits, act);
+          const uint32_t rk = (uint32_t)__popcll(peers & lanemask_lt());
+          uint32_t base = 0;
+          if (valid) base = wc[q];
+          if (valid && rk == 0) wc[q] = (uint16_t)(base + (uint32_t)__popcll(peers));
+          code[r] = (q << 16) | (base + rk);
+        } else {
+          // keys only: any order inside a bucket is the same output
+          const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
+          const uint64_t act = __ballot(valid);
+          uint32_t rk = 0;
+          if (act == ~0ull && __all(q == q0)) {
+            uint32_t b0 = 0;
+            if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
+            rk = __builtin_amdgcn_readfirstlane(b0) + l;
+          } else if (valid) {
+            rk = atomicAdd(&tcnt[q], 1u);
+          }
+          code[r] = (q << 16) | rk;
+        }
       }
       __syncthreads();
-      // 3. per bucket: wave offsets (exclusive over waves) and tile counts
-      for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-        uint32_t run = 0;
+      if (PAY) {
+        // per bucket: wave offsets (exclusive over waves) and tile counts
+        for (uint32_t q = threadIdx.x; q < nb; q += NT) {
+          uint32_t run = 0;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-          const uint32_t v = wcnt[ww * nb + q];
-          wcnt[ww * nb + q] = (uint16_t)run;
-          run += v;
+          for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t v = wcnt[ww * nb + q];
+            wcnt[ww * nb + q] = (uint16_t)run;
+            run += v;
+          }
+          tcnt[q] = run;
         }
-        tcnt[q] = run;
-        tstart[q] = run;
+        __syncthreads();
       }
+      for (uint32_t q = threadIdx.x; q < nb; q += NT) tstart[q] = tcnt[q];
       __syncthreads();
       block_scan_array<NT, false>(tstart, nb, red);
-      // 4. stage keys in bucket order
+      // stage keys in bucket order
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
         if (i < tn) {
           const uint32_t q = code[r] >> 16;
-          const uint32_t pos = tstart[q] + wc[q] + (code[r] & 0xffffu);
+          const uint32_t pos = tstart[q] + (PAY ? wc[q] : 0u) + (code[r] & 0xffffu);
           if (pos < (uint32_t)TS) {
             sk[pos] = key[r];
             if (PAY) sv[pos] = val[r];
@@ -675,38 +912,239 @@ __global__ __launch_bounds__(NT) void k_scatter(Plan p, int L, LevelIO io, uint3
         }
       }
       __syncthreads();
-      // 5. write runs: consecutive staged keys of one bucket are consecutive in HBM
-      for (uint32_t i = threadIdx.x; i < tn; i += NT) {
-        const uint32_t q = sb[i];
-        const uint64_t dst = nd.off + runoff[q] + (i - tstart[q]);
-        const uint64_t kv = sk[i];
-        if (dst >= nd.off + nd.len) {
-          flag_internal(c);
-          continue;
+      // write runs: consecutive staged keys of one bucket are consecutive in HBM
+      if (PCF_SC_BATCH_WRITE) {
+        // the LDS reads of all of a thread's keys are issued first
+        constexpr int WPT = TS / NT;
+        uint32_t wq[WPT], wo[WPT];
+        uint64_t wk[WPT];
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+          const uint32_t i = threadIdx.x + k * NT;
+          wq[k] = i < tn ? sb[i] : 0u;
+          wk[k] = i < tn ? sk[i] : 0ull;
         }
-        dk[dst] = kv;
-        if (PAY) dv[dst] = sv[i];
-        if (cmapf[q]) {
-          const unsigned long long im = img_of<KT>(kv);
-          atomicMin(&mmlo[q], im);
-          atomicMax(&mmhi[q], im);
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) wo[k] = runoff[wq[k]] - tstart[wq[k]];
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+          const uint32_t i = threadIdx.x + k * NT;
+          if (i < tn) {
+            const uint64_t dst = nd.off + (uint32_t)(wo[k] + i);
+            if (dst >= nd.off + nd.len) {
+              flag_internal(c);
+              continue;
+            }
+            dk[dst] = wk[k];
+            if (PAY) dv[dst] = sv[i];
+          }
+        }
+      } else {
+        for (uint32_t i = threadIdx.x; i < tn; i += NT) {
+          const uint32_t q = sb[i];
+          const uint64_t dst = nd.off + runoff[q] + (i - tstart[q]);
+          const uint64_t kv = sk[i];
+          if (dst >= nd.off + nd.len) {
+            flag_internal(c);
+            continue;
+          }
+          dk[dst] = kv;
+          if (PAY) dv[dst] = sv[i];
         }
       }
       __syncthreads();
       for (uint32_t q = threadIdx.x; q < nb; q += NT) {
         runoff[q] += tcnt[q];
+        tcnt[q] = 0u;
+        if (PAY) {
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) wcnt[ww * nb + q] = 0;
+          for (int ww = 0; ww < NW; ++ww) wcnt[ww * nb + q] = 0;
+        }
       }
       __syncthreads();
     }
-    // child ranges for the next level
+    // this chunk's range of every child that is a node of the next level
+    MinMax* mm = p.mm[s] + nd.cm_off;
+    for (uint32_t q = threadIdx.x; q < nb; q += NT)
+      if (cmapf[q]) mm[(uint64_t)q * C + un.chunk] = MinMax{mmlo[q], mmhi[q]};
+    __syncthreads();
+  }
+}
+
+
+// Keys only: tile ranks from LDS atomics (order inside a bucket is not
+// observable for keys alone), counters double-buffered across tiles so a tile
+// costs three barriers: rank | scan | stage | write.
+template <int KT, int NT, int TS>
+__global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO io, uint32_t max_bins,
+                                                     uint32_t nbmax) {
+  constexpr int NW = NT / 64;
+  constexpr int PW = TS / NW;
+  constexpr int R = PW / 64;
+  static_assert(PW % 64 == 0, "tile must split into whole wave rounds");
+  extern __shared__ __align__(16) unsigned char lds[];
+  const ScatterKeysLds lay = scatter_keys_lds(max_bins, nbmax, TS);
+  uint16_t* tab = reinterpret_cast<uint16_t*>(lds + lay.tab);
+  uint32_t* runoff2 = reinterpret_cast<uint32_t*>(lds + lay.runoff);  // [2][nbmax]
+  uint32_t* tstart2 = reinterpret_cast<uint32_t*>(lds + lay.tstart);  // [2][nbmax + 1]
+  uint32_t* tcnt2 = reinterpret_cast<uint32_t*>(lds + lay.tcnt);      // [2][nbmax]
+  unsigned long long* mmlo = reinterpret_cast<unsigned long long*>(lds + lay.mmlo);
+  unsigned long long* mmhi = reinterpret_cast<unsigned long long*>(lds + lay.mmhi);
+  uint8_t* cmapf = reinterpret_cast<uint8_t*>(lds + lay.cmapf);
+  uint64_t* sk = reinterpret_cast<uint64_t*>(lds + lay.sk);
+  uint16_t* sb = reinterpret_cast<uint16_t*>(lds + lay.sb);
+
+  const int s = L & 1;
+  Ctl* c = p.ctl;
+  const uint32_t nu = c->lv[L].num_units;
+  if (!ctl_ok(c)) return;
+  const int l = lane_id(), w = wave_id();
+  uint64_t* dk = reinterpret_cast<uint64_t*>(io.dst_keys);
+  uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
+
+  for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+    const Unit un = p.units[s][u];
+    const Node& nd = p.nodes[s][un.node];
+    uint32_t cb, ce;
+    chunk_range(nd, un.chunk, cb, ce);
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
+    if (nd.state == NS_DONE) {
+      uint64_t* o = ok_ + nd.off;
+      if ((const void*)o != nd.src)
+        for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) o[i] = src[i];
+      continue;
+    }
+    const uint32_t nb = nd.nb, C = nd.nchunks;
+    if (nd.kind == NK_PCF)
+      for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = p.table[s][nd.table_off + i];
+    const uint32_t* bs = p.bstart[s] + nd.aux_off;
+    const int32_t* cm = p.cmap[s] + nd.aux_off;
+    const uint32_t* col = p.cm[s] + nd.cm_off;
+    bool glb = false;
     for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-      if (cmapf[q] && mmlo[q] != ~0ull) {
-        Node& ch = p.nodes[s1][cm[q]];
-        atomicMin(&ch.min_img, mmlo[q]);
-        atomicMax(&ch.max_img, mmhi[q]);
+      runoff2[q] = bs[q] + col[(uint64_t)q * C + un.chunk];
+      tcnt2[q] = 0u;
+      const bool g = cm[q] >= 0;
+      cmapf[q] = g ? 1 : 0;
+      glb |= g;
+      mmlo[q] = ~0ull;
+      mmhi[q] = 0ull;
+    }
+    const bool any_glb = __syncthreads_or(glb) != 0;
+    const Bucketer<KT> bk = make_bucketer<KT>(nd, tab);
+
+    uint64_t key[R], nkey[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = w * PW + r * 64 + l;
+      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(src + cb + i) : 0ull;
+    }
+    uint32_t par = 0;
+    for (uint32_t t0 = cb; t0 < ce; t0 += TS, par ^= 1u) {
+      const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
+      uint32_t* runoff = runoff2 + par * nbmax;
+      uint32_t* runoff_n = runoff2 + (par ^ 1u) * nbmax;
+      uint32_t* tstart = tstart2 + par * (nbmax + 1);
+      uint32_t* tcnt = tcnt2 + par * nbmax;
+      uint32_t* tcnt_n = tcnt2 + (par ^ 1u) * nbmax;
+#pragma unroll
+      for (int r = 0; r < R; ++r) key[r] = nkey[r];
+      const uint32_t t1 = t0 + TS;
+      if (t1 < ce) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(src + t1 + i) : 0ull;
+        }
       }
+      // A: bucket, rank inside the tile's bucket, child ranges
+      uint32_t code[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = w * PW + r * 64 + l;
+        const bool valid = i < tn;
+        uint32_t q = valid ? bk(key[r]) : 0u;
+        if (q >= nb) {  // range check: cannot happen for a consistent model
+          flag_internal(c);
+          q = nb - 1;
+        }
+        const uint32_t q0 = __shfl(q, 0, 64);
+        const uint64_t act = __ballot(valid);
+        const bool uni = act == ~0ull && __all(q == q0);
+        uint32_t rk = 0;
+        if (uni) {
+          // the whole wave in one bucket (runs of duplicates)
+          uint32_t b0 = 0;
+          if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
+          rk = __shfl(b0, 0, 64) + l;
+          if (any_glb && cmapf[q0]) {
+            const uint64_t im = img_of<KT>(key[r]);
+            const uint64_t wlo = wave_min_u64(im), whi = wave_max_u64(im);
+            if (l == 0) {
+              atomicMin(&mmlo[q0], (unsigned long long)wlo);
+              atomicMax(&mmhi[q0], (unsigned long long)whi);
+            }
+          }
+        } else if (valid) {
+          rk = atomicAdd(&tcnt[q], 1u);
+          if (any_glb && cmapf[q]) {
+            const unsigned long long im = img_of<KT>(key[r]);
+            atomicMin(&mmlo[q], im);
+            atomicMax(&mmhi[q], im);
+          }
+        }
+        code[r] = (q << 16) | rk;
+      }
+      __syncthreads();
+      // B: bucket starts of the tile (wave 0), next tile's run offsets and counters
+      if (w == 0) {
+        uint32_t carry = 0;
+        for (uint32_t q0 = 0; q0 < nb; q0 += 64) {
+          const uint32_t q = q0 + l;
+          const uint32_t v = q < nb ? tcnt[q] : 0u;
+          const uint32_t x = wave_incl_scan(v);
+          if (q < nb) tstart[q] = carry + x - v;
+          carry += __shfl(x, 63, 64);
+        }
+      }
+      for (uint32_t q = threadIdx.x; q < nb; q += NT) {
+        runoff_n[q] = runoff[q] + tcnt[q];
+        tcnt_n[q] = 0u;
+      }
+      __syncthreads();
+      // C: stage keys in bucket order
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = w * PW + r * 64 + l;
+        if (i < tn) {
+          const uint32_t q = code[r] >> 16;
+          const uint32_t pos = tstart[q] + (code[r] & 0xffffu);
+          if (pos < (uint32_t)TS) {
+            sk[pos] = key[r];
+            sb[pos] = (uint16_t)q;
+          } else {
+            flag_internal(c);
+          }
+        }
+      }
+      __syncthreads();
+      // D: write runs (consecutive staged keys of one bucket go to consecutive
+      // addresses); the next tile's rank phase touches only the other buffers
+      for (uint32_t i = threadIdx.x; i < tn; i += NT) {
+        const uint32_t q = sb[i];
+        const uint64_t dst = nd.off + runoff[q] + (i - tstart[q]);
+        if (dst >= nd.off + nd.len) {
+          flag_internal(c);
+          continue;
+        }
+        dk[dst] = sk[i];
+      }
+    }
+    __syncthreads();
+    if (any_glb) {
+      MinMax* mm = p.mm[s] + nd.cm_off;
+      for (uint32_t q = threadIdx.x; q < nb; q += NT)
+        if (cmapf[q]) mm[(uint64_t)q * C + un.chunk] = MinMax{mmlo[q], mmhi[q]};
     }
     __syncthreads();
   }
@@ -715,12 +1153,15 @@ __global__ __launch_bounds__(NT) void k_scatter(Plan p, int L, LevelIO io, uint3
 // ---------------------------------------------------------------------------
 // K5: finish an array inside one workgroup's LDS
 // ---------------------------------------------------------------------------
-// Algorithm 1 with the paper's parameters alpha = beta = gamma = delta =
-// floor(m^{3/4}) and tau: PCF levels run in LDS (out-of-order bucket writes
-// through LDS atomics), buckets below tau get a counting rank, failed buckets
-// (>= delta) an in-LDS bitonic sort.  Ties are ordered by the key's position
-// in the item, which is the input order because every global scatter before
-// this one was stable.
+// Algorithm 1 inside LDS.  Every level trains the PCF on all m keys of its
+// array (alpha = m: Sec. 3.2 allows training on all elements) with beta = m
+// equal-width bins and gamma = alpha, so the bucket of a key,
+// floor(b_{i(x)} gamma / alpha) = b_{i(x)}, is its bin: buckets hold about one
+// key.  Buckets below tau get a counting rank, buckets of tau keys or more
+// recurse, failed buckets (>= delta = floor(m^{3/4})) get the standard sort
+// (in-LDS bitonic).  Ties are ordered by the key's position in the item,
+// which is its input order whenever a payload makes order observable (the
+// global scatters before this one are then stable).
 template <int KT, int CAP, int NT>
 __device__ void k5_bitonic(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e) {
   const uint32_t n = e - s;
@@ -761,65 +1202,54 @@ __device__ void k5_bitonic(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e) {
   __syncthreads();
 }
 
-// One PCF level on the LDS range [s, e) (a node of depth `depth`).
+// One PCF level on the LDS range [s, e) (a node of depth `depth`) with all of
+// its keys as the training set and one bin per key.
 template <int KT, int CAP, int NT>
-__device__ void k5_level(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e, uint64_t nseed,
-                         uint32_t depth, uint64_t lo, uint64_t hi, uint32_t tau) {
+__device__ void k5_level(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e, uint32_t depth,
+                         uint64_t lo, uint64_t hi, uint32_t tau) {
   constexpr int EPT = (CAP + NT - 1) / NT;
   const uint32_t n = e - s;
-  const uint32_t r = root34(n);
-  const uint32_t alpha = r, beta = r, gamma = r, delta = r, nb = r + 1;
+  const uint32_t beta = n, delta = root34(n);
   BinFn f;
   if (!bin_setup<KT>(f, lo, hi, beta)) {
     k5_bitonic<KT, CAP, NT>(sm, s, e);
     return;
   }
-  for (uint32_t i = threadIdx.x; i <= nb; i += NT) {
-    sm.hist[i] = 0u;
-    sm.cnt[i] = 0u;
-  }
-  __syncthreads();
-  for (uint32_t j = threadIdx.x; j < alpha; j += NT) {
-    const uint32_t q = s + sample_pos(nseed, j, n);
-    atomicAdd(&sm.hist[bin_of<KT>(f, bits_of_img<KT>(sm.key[q]))], 1u);
-  }
-  __syncthreads();
-  block_scan_array<NT, true>(sm.hist, beta + 1, sm.red);
-  for (uint32_t i = threadIdx.x; i <= beta; i += NT)
-    sm.tab[i] = (uint16_t)(((uint64_t)sm.hist[i] * gamma) / alpha);
+  for (uint32_t i = threadIdx.x; i <= beta + 1; i += NT) sm.cnt[i] = 0u;
   __syncthreads();
   uint64_t kk[EPT];
-  uint32_t pc[EPT];  // pos | bucket << 16
+  uint32_t pb[EPT];  // pos | bin << 16
   uint32_t rk[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const uint32_t i = s + threadIdx.x + k * NT;
     if (i < e) {
       kk[k] = sm.key[i];
-      const uint32_t q = sm.tab[bin_of<KT>(f, bits_of_img<KT>(kk[k]))];
-      pc[k] = (uint32_t)sm.pos[i] | (q << 16);
-      rk[k] = atomicAdd(&sm.cnt[q], 1u);
+      const uint32_t b = bin_of<KT>(f, bits_of_img<KT>(kk[k]));
+      pb[k] = (uint32_t)sm.pos[i] | (b << 16);
+      rk[k] = atomicAdd(&sm.cnt[b], 1u);
     }
   }
   __syncthreads();
-  block_scan_array<NT, false>(sm.cnt, nb, sm.red);
-  if (threadIdx.x == 0) sm.cnt[nb] = n;
+  block_scan_array<NT, false>(sm.cnt, beta + 1, sm.red);
+  if (threadIdx.x == 0) sm.cnt[beta + 1] = n;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const uint32_t i = s + threadIdx.x + k * NT;
     if (i < e) {
-      const uint32_t q = pc[k] >> 16;
-      const uint32_t d = s + sm.cnt[q] + rk[k];
+      const uint32_t b = pb[k] >> 16;
+      const uint32_t a = sm.cnt[b], z = sm.cnt[b + 1];
+      const uint32_t d = s + a + rk[k];
       if (d >= e) continue;  // range check: cannot happen for consistent counts
       sm.key[d] = kk[k];
-      sm.pos[d] = (uint16_t)(pc[k] & 0xffffu);
-      sm.seg[d] = (s + sm.cnt[q]) | ((s + sm.cnt[q + 1]) << 16);
+      sm.pos[d] = (uint16_t)(pb[k] & 0xffffu);
+      sm.seg[d] = (s + a) | ((s + z) << 16);
     }
   }
-  // buckets of at least tau keys need more work (recursion or, when they
-  // failed, the standard sort)
-  for (uint32_t q = threadIdx.x; q < nb; q += NT) {
+  // bins of at least tau keys need more work: recursion, or the standard sort
+  // when they failed (>= delta)
+  for (uint32_t q = threadIdx.x; q <= beta; q += NT) {
     const uint32_t a = sm.cnt[q], b = sm.cnt[q + 1];
     if (b - a >= tau) {
       const uint32_t slot = atomicAdd(&sm.nstk, 1u);
@@ -828,47 +1258,88 @@ __device__ void k5_level(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e, uint64
         sm.stk[slot][1] = s + b;
         sm.stk[slot][2] = (depth + 1) | ((b - a >= delta) ? 0x80000000u : 0u);
       } else {
-        sm.flag = 1;  // cannot happen: ranges >= tau are disjoint
+        sm.flag = 1;  // cannot happen: ranges of >= tau keys are disjoint
       }
     }
   }
   __syncthreads();
 }
 
+// Occupancy targets in waves per SIMD: 4 workgroups of 4 waves per CU for the
+// 2048-key class, 2 for 4096, 1 workgroup of 8 waves for 8192 (what their LDS
+// allows).
+template <int CAP>
+struct K5Occ {
+  static constexpr int v = CAP <= 2048 ? 4 : 2;
+};
+
 template <int KT, int CAP, int NT, int PAY>
-__global__ __launch_bounds__(NT) void k_lds_sort(Plan p, int cls) {
+__global__ __launch_bounds__(NT, K5Occ<CAP>::v) void k_lds_sort(Plan p, int cls) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   K5Smem<KT, CAP, NT>& sm = *reinterpret_cast<K5Smem<KT, CAP, NT>*>(lds_raw);
+  constexpr int EPT = (CAP + NT - 1) / NT;
   Ctl* c = p.ctl;
   const uint32_t total = c->item_count[cls] < p.cap_items[cls] ? c->item_count[cls]
                                                                 : p.cap_items[cls];
   const uint32_t tau = p.pol.tau;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
-  while (true) {
-    if (threadIdx.x == 0) {
-      sm.item = atomicAdd(&c->item_next[cls], 1u);
-      sm.sh[3] = ctl_ok(c) ? 1u : 0u;
+  unsigned long long done_keys = 0;
+  // static assignment of items to workgroups (a shared work counter would be
+  // a same-address atomic per item); the next item's keys are prefetched
+  // into registers while this one is sorted
+  uint64_t pre[EPT];
+  if (PCF_K5_PREFETCH && blockIdx.x < total) {
+    const Item it0 = p.items[cls][blockIdx.x];
+    const uint64_t* s0 = reinterpret_cast<const uint64_t*>(it0.src);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const uint32_t i = threadIdx.x + k * NT;
+      pre[k] = i < it0.len ? __builtin_nontemporal_load(s0 + i) : 0ull;
     }
+  }
+  for (uint32_t ii = blockIdx.x; ii < total; ii += gridDim.x) {
+    if (threadIdx.x == 0) sm.sh[3] = ctl_ok(c) ? 1u : 0u;
     __syncthreads();
-    const uint32_t ii = sm.item;
     const bool go = sm.sh[3] != 0;
     __syncthreads();
-    if (ii >= total || !go) return;
+    if (!go) break;
     const Item it = p.items[cls][ii];
     const uint32_t m = it.len;
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(it.src);
-    // load, validate (roots), range
+    done_keys += m;
+    if (!PCF_K5_PREFETCH) {
+      const uint64_t* s0 = reinterpret_cast<const uint64_t*>(it.src);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        pre[k] = i < m ? s0[i] : 0ull;
+      }
+    }
+    // keys to LDS, validate (roots), range
     uint64_t lo = ~0ull, hi = 0ull;
     bool bad = false;
-    for (uint32_t i = threadIdx.x; i < m; i += NT) {
-      const uint64_t bits = src[i];
-      if (KT == KT_F64 && (it.flags & IF_ROOT)) bad |= !f64_bits_valid(bits);
-      const uint64_t im = img_of<KT>(bits);
-      sm.key[i] = im;
-      sm.pos[i] = (uint16_t)i;
-      sm.seg[i] = 0u | (m << 16);
-      lo = im < lo ? im : lo;
-      hi = im > hi ? im : hi;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const uint32_t i = threadIdx.x + k * NT;
+      if (i < m) {
+        const uint64_t bits = pre[k];
+        if (KT == KT_F64 && (it.flags & IF_ROOT)) bad |= !f64_bits_valid(bits);
+        const uint64_t im = img_of<KT>(bits);
+        sm.key[i] = im;
+        sm.pos[i] = (uint16_t)i;
+        sm.seg[i] = 0u | (m << 16);
+        lo = im < lo ? im : lo;
+        hi = im > hi ? im : hi;
+      }
+    }
+    const uint32_t nii = ii + gridDim.x;
+    if (PCF_K5_PREFETCH && nii < total) {
+      const Item nit = p.items[cls][nii];
+      const uint64_t* s1 = reinterpret_cast<const uint64_t*>(nit.src);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        pre[k] = i < nit.len ? __builtin_nontemporal_load(s1 + i) : 0ull;
+      }
     }
     if (threadIdx.x == 0) {
       sm.flag = 0;
@@ -882,7 +1353,6 @@ __global__ __launch_bounds__(NT) void k_lds_sort(Plan p, int cls) {
       __syncthreads();
       continue;
     }
-    const uint64_t seed0 = node_seed(p.seed, it.seg, it.depth, it.rel);
     if (lo == hi) {
       // single-valued: input order is the answer
       for (uint32_t i = threadIdx.x; i < m; i += NT) sm.seg[i] = i | ((i + 1) << 16);
@@ -890,9 +1360,9 @@ __global__ __launch_bounds__(NT) void k_lds_sort(Plan p, int cls) {
     } else if (it.flags & IF_STD) {
       k5_bitonic<KT, CAP, NT>(sm, 0, m);
     } else if (m >= tau) {
-      k5_level<KT, CAP, NT>(sm, 0, m, seed0, it.depth, lo, hi, tau);
+      k5_level<KT, CAP, NT>(sm, 0, m, it.depth, lo, hi, tau);
       // ranges still at or above tau: recurse (or standard sort if failed)
-      while (true) {
+      while (sm.nstk != 0) {
         __syncthreads();
         if (threadIdx.x == 0) {
           const uint32_t k = sm.nstk < K5Cfg<CAP>::SMAX ? sm.nstk : K5Cfg<CAP>::SMAX;
@@ -919,22 +1389,22 @@ __global__ __launch_bounds__(NT) void k_lds_sort(Plan p, int cls) {
         }
         block_minmax_u64<NT>(rlo, rhi, sm.red64);
         if (rlo == rhi) {
-          if (rfail) k5_bitonic<KT, CAP, NT>(sm, rs, re);
-          // else: the counting rank orders equal keys by position
+          // equal keys: order them by position (the standard sort does it in
+          // O(m log^2 m); a counting rank would be quadratic)
+          k5_bitonic<KT, CAP, NT>(sm, rs, re);
         } else if (rfail) {
           k5_bitonic<KT, CAP, NT>(sm, rs, re);
         } else {
-          const uint64_t ns = node_seed(p.seed, it.seg, rdepth, it.rel + rs);
-          k5_level<KT, CAP, NT>(sm, rs, re, ns, rdepth, rlo, rhi, tau);
+          k5_level<KT, CAP, NT>(sm, rs, re, rdepth, rlo, rhi, tau);
         }
       }
     }
     __syncthreads();
-    // counting rank inside final segments; all reads (LDS keys and the
-    // payload, which may live in the very range being written) happen before
-    // the barrier, all writes after it
-    constexpr int EPT = (CAP + NT - 1) / NT;
+    // counting rank inside final segments.  With a payload, all reads (LDS
+    // keys and the payload, which may live in the very range being written)
+    // happen before a barrier and all writes after it.
     uint32_t rr[EPT], vv[EPT];
+    uint64_t* ok = ok_ + it.off;
 #pragma unroll
     for (int kq = 0; kq < EPT; ++kq) {
       const uint32_t i = threadIdx.x + kq * NT;
@@ -953,26 +1423,35 @@ __global__ __launch_bounds__(NT) void k_lds_sort(Plan p, int cls) {
           }
         }
         rr[kq] = rnk;
-        if (PAY) vv[kq] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
+        if (PAY) {
+          vv[kq] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
+        } else if (rnk < m) {
+          ok[rnk] = bits_of_img<KT>(k);
+        } else {
+          flag_internal(c);
+        }
       }
     }
-    __syncthreads();
-    uint64_t* ok = ok_ + it.off;
+    if (PAY) {
+      __syncthreads();
 #pragma unroll
-    for (int kq = 0; kq < EPT; ++kq) {
-      const uint32_t i = threadIdx.x + kq * NT;
-      if (i < m) {
-        const uint32_t rnk = rr[kq];
-        if (rnk >= m) {
-          flag_internal(c);
-          continue;
+      for (int kq = 0; kq < EPT; ++kq) {
+        const uint32_t i = threadIdx.x + kq * NT;
+        if (i < m) {
+          const uint32_t rnk = rr[kq];
+          if (rnk >= m) {
+            flag_internal(c);
+            continue;
+          }
+          ok[rnk] = bits_of_img<KT>(sm.key[i]);
+          p.out_vals[it.off + rnk] = vv[kq];
         }
-        ok[rnk] = bits_of_img<KT>(sm.key[i]);
-        if (PAY) p.out_vals[it.off + rnk] = vv[kq];
       }
     }
     __syncthreads();
   }
+  if (p.pol.prof && threadIdx.x == 0 && done_keys)
+    atomicAdd(&c->item_keys[cls], done_keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -982,16 +1461,20 @@ __global__ __launch_bounds__(NT) void k_lds_sort(Plan p, int cls) {
   template __global__ void k_range<KT, 256>(Plan);                                       \
   template __global__ void k_fit<KT, 1024>(Plan, int, int);                              \
   template __global__ void k_count<KT, 512>(Plan, int);                                  \
+  template __global__ void k_scatter_keys<KT, 512, 8192>(Plan, int, LevelIO, uint32_t,   \
+                                                         uint32_t);                      \
+  template __global__ void k_scatter_keys<KT, 512, 4096>(Plan, int, LevelIO, uint32_t,   \
+                                                         uint32_t);                      \
   template __global__ void k_scatter<KT, 512, 4096, 0>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
   template __global__ void k_scatter<KT, 512, 4096, 1>(Plan, int, LevelIO, uint32_t,     \
-                                                       uint32_t);                        \
-  template __global__ void k_scatter<KT, 512, 2048, 0>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
   template __global__ void k_scatter<KT, 512, 2048, 1>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
   template __global__ void k_lds_sort<KT, 2048, 256, 0>(Plan, int);                      \
   template __global__ void k_lds_sort<KT, 2048, 256, 1>(Plan, int);                      \
+  template __global__ void k_lds_sort<KT, 4096, 256, 0>(Plan, int);                      \
+  template __global__ void k_lds_sort<KT, 4096, 256, 1>(Plan, int);                      \
   template __global__ void k_lds_sort<KT, 8192, 512, 0>(Plan, int);                      \
   template __global__ void k_lds_sort<KT, 8192, 512, 1>(Plan, int);
 

@@ -14,7 +14,9 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpcfsort.so")
+# PCF_LIB_PATH selects another build of the same library (e.g. a variant
+# compiled with different tile sizes for tuning)
+LIB_PATH = os.environ.get("PCF_LIB_PATH") or os.path.join(HERE, "libpcfsort.so")
 
 OK = 0
 ERR_INVALID_ARGUMENT = 1
@@ -35,7 +37,11 @@ EXPORTS = [
     "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
+    "pcf_profile_enable", "pcf_profile_read", "pcf_kernel_name",
 ]
+
+KERNEL_KINDS = ["setup", "range", "fit", "count", "colscan", "classify", "scatter", "lds_small",
+                "lds_big"]
 
 
 class PcfError(RuntimeError):
@@ -55,6 +61,10 @@ class Policy(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("keys", ctypes.c_double)]
 
 
 class ServeConfig(ctypes.Structure):
@@ -121,6 +131,9 @@ def load(path: str = LIB_PATH):
         "pcf_serve_release": (_INT, [_VP, _U64]),
         "pcf_serve_get_stats": (_INT, [_VP, ctypes.POINTER(ServeStats)]),
         "pcf_serve_destroy": (_INT, [_VP]),
+        "pcf_profile_enable": (_INT, [_INT]),
+        "pcf_profile_read": (_INT, [ctypes.POINTER(KernelStat), _INT]),
+        "pcf_kernel_name": (ctypes.c_char_p, [_INT]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -294,3 +307,15 @@ def pcf_autotune(key_type: int, with_payload: bool, out_json: str) -> None:
 
 def pcf_load_tuning(path: str) -> None:
     _check(load().pcf_load_tuning(path.encode()), "pcf_load_tuning")
+
+
+def pcf_profile_enable(on: bool = True) -> None:
+    _check(load().pcf_profile_enable(int(on)), "pcf_profile_enable")
+
+
+def pcf_profile_read(reset: bool = False) -> dict:
+    """Per-kernel totals: {name: {"launches", "ms", "keys"}}."""
+    arr = (KernelStat * len(KERNEL_KINDS))()
+    _check(load().pcf_profile_read(arr, int(reset)), "pcf_profile_read")
+    return {KERNEL_KINDS[i]: {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
+                              "keys": float(arr[i].keys)} for i in range(len(KERNEL_KINDS))}
