@@ -126,3 +126,76 @@ def test_in_place_and_all_equal(P, oracle):
     y = np.full(300_000, 3.5)
     _, gi = P.pcf_argsort(to_dev(y))
     np.testing.assert_array_equal(to_host(gi, np.uint32), np.arange(300_000, dtype=np.uint32))
+
+
+def test_level_trace_keys_only_multiset(P, oracle):
+    """Keys alone are scattered with unstable ranks (equal keys are the same
+    bits): the model and the sizes are exact, each bucket is the oracle's as
+    a multiset."""
+    import torch
+    x = datagen.f64("normal", 250_000, 41)
+    alpha, beta, gamma = 4096, 4095, 255
+    nseed = oracle.node_seed(9, 0, 0, 0)
+    banner("level trace keys only")
+    ref = oracle.level(x, alpha, beta, gamma, nseed)
+    got = P.pcf_level_trace(to_dev(x), alpha, beta, gamma, nseed)
+    np.testing.assert_array_equal(got["b"], ref.b)
+    np.testing.assert_array_equal(got["T"], ref.T)
+    np.testing.assert_array_equal(got["sizes"], ref.sizes)
+    part = to_host(got["part_keys"], np.float64)
+    bounds = np.concatenate([[0], np.cumsum(ref.sizes.astype(np.int64))])
+    for j in range(gamma + 1):
+        a, b = bounds[j], bounds[j + 1]
+        np.testing.assert_array_equal(np.sort(part[a:b]), np.sort(ref.part_keys[a:b]))
+
+
+SEG_SIZES = [0, 1, 5, 99, 100, 101, 2047, 2048, 2049, 4096, 4097, 8192, 8193, 0, 20_000,
+             150_000, 3, 70_001]
+
+
+def _segments(kind):
+    rng = np.random.default_rng(5)
+    parts = []
+    for i, m in enumerate(SEG_SIZES):
+        if kind == "f64":
+            parts.append(datagen.f64(datagen.F64_DISTS[i % 6], m, 300 + i))
+        else:
+            parts.append(datagen.u64(datagen.U64_KINDS[i % 3], m, 400 + i, distinct=5000)
+                         if m else np.zeros(0, np.uint64))
+    keys = np.concatenate(parts)
+    offsets = np.zeros(len(SEG_SIZES) + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(SEG_SIZES)
+    vals = np.concatenate([rng.integers(0, 2**32, m, dtype=np.uint64).astype(np.uint32)
+                           for m in SEG_SIZES])
+    return keys, offsets, vals
+
+
+@pytest.mark.parametrize("kind", ["f64", "u64"])
+@pytest.mark.parametrize("payload", [False, True])
+def test_segmented_matches_oracle(P, oracle, kind, payload):
+    banner(f"segmented {kind} payload={payload}")
+    keys, offsets, vals = _segments(kind)
+    ref_k, ref_v = oracle.sort_segmented(keys, offsets, vals if payload else None)
+    dt = np.float64 if kind == "f64" else np.uint64
+    gk, gv = P.pcf_sort_segmented(to_dev(keys), to_dev(offsets.view(np.int64)),
+                                  to_dev(vals) if payload else None)
+    np.testing.assert_array_equal(to_host(gk, dt), ref_k)
+    if payload:
+        np.testing.assert_array_equal(to_host(gv, np.uint32), ref_v)
+
+
+def test_segmented_equals_per_array_plain(P):
+    """Batching changes nothing: each segment equals the plain sort of it."""
+    banner("segmented vs plain per segment")
+    keys, offsets, vals = datagen.segments(num=64, lo_log2=6, hi_log2=17, seed=12)
+    gk, gv = P.pcf_sort_segmented(to_dev(keys), to_dev(offsets.view(np.int64)), to_dev(vals))
+    gk = to_host(gk, np.float64)
+    gv = to_host(gv, np.uint32)
+    for s in range(64):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        if b == a:
+            continue
+        pk, pi = P.pcf_argsort(to_dev(keys[a:b]))
+        np.testing.assert_array_equal(gk[a:b], to_host(pk, np.float64))
+        # the payload is the in-segment index, so it equals the argsort
+        np.testing.assert_array_equal(gv[a:b], to_host(pi, np.uint32))
