@@ -104,14 +104,27 @@ int pcf_argsort(int key_type, const void *d_keys_in, void *d_keys_out, uint32_t 
  * uint32 payload d_vals_in -> d_vals_out (both NULL for keys only; with a
  * payload every segment must be shorter than 2^32).  d_offsets: device array
  * of num_segments + 1 non-decreasing uint64 CSR offsets, d_offsets[0] = 0;
- * empty segments are allowed.  The whole batch runs as one fixed launch chain
- * that is captured once per (key type, payload, size class) into a hipGraph
- * and replayed; parameters come from the autotuned policy table.
+ * empty segments are allowed.  total_keys = d_offsets[num_segments] < 2^32.
+ * With a caller workspace (d_ws != NULL) the batch runs as one fixed launch
+ * chain (enough levels for any input of total_keys keys, empty levels exit at
+ * once) that is captured into a hipGraph on the first call with a given
+ * argument set (device, key type, buffer pointers, sizes, d_status, policy)
+ * and replayed by later calls with the same set; up to 16 executable graphs
+ * are cached (least recently used evicted).  The graph reads the buffers'
+ * contents at replay time, so a caller may refill them between calls.  With
+ * d_ws == NULL, with profiling on, or with PCF_NO_GRAPH set in the
+ * environment, the launches are made one by one.  Stream-ordered: returns
+ * after enqueue when d_status is given, else waits and returns the outcome.
  */
 int pcf_sort_segmented(int key_type, const void *d_keys_in, void *d_keys_out,
                        const uint32_t *d_vals_in, uint32_t *d_vals_out,
                        const uint64_t *d_offsets, uint32_t num_segments, size_t total_keys,
                        void *d_ws, size_t ws_bytes, int32_t *d_status, void *stream);
+
+/* Graph cache counters of pcf_sort_segmented (captures, replays, entries held). */
+int pcf_graph_stats(uint64_t *captures, uint64_t *replays, uint64_t *cached);
+/* Waits for and destroys every cached graph (e.g. before freeing its buffers). */
+int pcf_graph_clear(void);
 
 /*
  * Diagnostic: run exactly one model-based bucketing level (Sec. 3.3 with the

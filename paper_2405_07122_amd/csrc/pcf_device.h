@@ -7,6 +7,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace pcf {
@@ -201,12 +202,15 @@ struct LevelCtr {
 
 struct Ctl {
   int32_t status;      // 0 or the data error (PCF_ERR_INVALID_KEY)
-  uint32_t overflow;   // a capacity bound was exceeded (library bug guard)
+  uint32_t overflow;   // a capacity bound was exceeded (library bug guard); kernels
+                       // read status and overflow together as one 64-bit word
   uint32_t item_count[3];
   uint32_t n_radix_nodes, n_fail_items, n_done_nodes;
   unsigned long long item_keys[3];  // keys in the LDS items of each class (profiling)
   LevelCtr lv[MAX_LEVELS];
 };
+
+static_assert(offsetof(Ctl, overflow) == 4, "status and overflow form one 64-bit word");
 
 struct PolicyDev {
   uint32_t max_buckets, target_child, bins_per_bucket, max_bins;

@@ -61,6 +61,8 @@ struct SortArgs {
 };
 
 int run_sort(const SortArgs& a);
+int graph_stats(uint64_t* captures, uint64_t* replays, uint64_t* cached);
+int graph_clear();
 
 pcf_policy current_policy();
 int device_cus();

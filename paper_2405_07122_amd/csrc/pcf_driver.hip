@@ -246,8 +246,23 @@ static int planned_levels(uint64_t n, uint32_t cap) {
   return d;
 }
 
+// Levels of a fixed launch chain (graph capture) that cover every input of n
+// keys: PCF levels shrink an array of m keys below root34(m), so PCF nodes
+// live only on the first `planned` levels; a failed bucket becomes a radix
+// node whose children's key range loses at least 8 of the 64 bits per level,
+// so at most 8 radix levels follow, plus one level on which single-valued
+// nodes are marked done.
+static int chain_levels(uint64_t n, uint32_t cap) {
+  return std::min(planned_levels(n, cap) + 9, MAX_LEVELS - 1);
+}
+
+// Enqueues one sort on a.stream.  fixed_levels == 0: the level loop reads back
+// the next level's size once the planned levels have run; fixed_levels > 0:
+// exactly that many levels are launched with no host synchronization (empty
+// levels exit at once), so the launches can be captured into a graph.
 template <int KT, int PAY>
-static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol) {
+static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
+                     int fixed_levels) {
   hipStream_t st = a.stream;
   const int cus = device_cus();
   if (cus <= 0) return PCF_ERR_UNSUPPORTED;
@@ -379,7 +394,9 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   int levels = 0;
   Ctl hc;
   for (int L = 0; L < planned || true; ++L) {
-    if (L >= planned) {
+    if (fixed_levels > 0) {
+      if (L >= fixed_levels) break;
+    } else if (L >= planned) {
       // read back the next level's size only once the planned levels have run
       PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
       PCF_HIP(hipStreamSynchronize(st));
@@ -468,13 +485,10 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), dim3(cus), dim3(K5_BIG_NT),
                        sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>), st, p, 2);
   });
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status,
+                     fixed_levels > 0 ? fixed_levels : -1);
   PCF_HIP(hipGetLastError());
-  if (a.d_status && !t_prof.on) {
-    PCF_HIP(hipMemcpyAsync(a.d_status, &p.ctl->status, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    return PCF_OK;
-  }
-  if (a.d_status)
-    PCF_HIP(hipMemcpyAsync(a.d_status, &p.ctl->status, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  if (fixed_levels > 0 || (a.d_status && !t_prof.on)) return PCF_OK;
   PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   PCF_HIP(hipStreamSynchronize(st));
   {
@@ -546,6 +560,150 @@ static int set_attrs() {
   return PCF_OK;
 }
 
+static int dispatch(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
+                    int has_pay, int fixed_levels) {
+  if (a.key_type == PCF_KEY_F64)
+    return has_pay ? run_typed<KT_F64, 1>(a, lay, ws, pol, fixed_levels)
+                   : run_typed<KT_F64, 0>(a, lay, ws, pol, fixed_levels);
+  return has_pay ? run_typed<KT_U64, 1>(a, lay, ws, pol, fixed_levels)
+                 : run_typed<KT_U64, 0>(a, lay, ws, pol, fixed_levels);
+}
+
+// ---- graph replay of segmented sorts ----------------------------------------
+// A segmented call with a caller workspace is captured once per argument set
+// (device, key type, buffers, sizes, policy) as the fixed launch chain and
+// replayed from then on; the executable graphs live in a small LRU cache.
+struct GraphKey {
+  int dev, kt, pay;
+  const void* kin;
+  void* kout;
+  const uint32_t* vin;
+  uint32_t* vout;
+  const uint64_t* off;
+  uint32_t nseg;
+  uint64_t n;
+  void* ws;
+  int32_t* dst;
+  pcf_policy pol;
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+  hipEvent_t done;  // recorded after the latest launch
+  uint64_t tick;
+};
+
+constexpr size_t GRAPH_CACHE = 16;
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+static uint64_t g_graph_tick = 0, g_graph_captures = 0, g_graph_replays = 0;
+static hipStream_t g_cap_stream[16] = {};
+
+static bool graphs_enabled() {
+  static const bool off = getenv("PCF_NO_GRAPH") != nullptr;
+  return !off;
+}
+
+static bool use_graph(const SortArgs& a) {
+  if (!a.offsets || a.trace || !graphs_enabled()) return false;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  return !g_prof_on;  // profiling records events per launch: eager path
+}
+
+static int run_graph(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
+                     int has_pay) {
+  GraphKey k;
+  std::memset(&k, 0, sizeof(k));  // padding takes part in the comparison
+  PCF_HIP(hipGetDevice(&k.dev));
+  if (k.dev < 0 || k.dev >= 16) return PCF_ERR_UNSUPPORTED;
+  k.kt = a.key_type;
+  k.pay = has_pay;
+  k.kin = a.keys_in;
+  k.kout = a.keys_out;
+  k.vin = a.vals_in;
+  k.vout = a.vals_out;
+  k.off = a.offsets;
+  k.nseg = a.nseg;
+  k.n = a.n;
+  k.ws = ws;
+  k.dst = a.d_status;
+  k.pol = pol;
+  std::lock_guard<std::mutex> g(g_graph_mu);
+  GraphEntry* e = nullptr;
+  for (auto& x : g_graphs)
+    if (std::memcmp(&x.key, &k, sizeof(k)) == 0) e = &x;
+  if (!e) {
+    if (!g_cap_stream[k.dev]) PCF_HIP(hipStreamCreateWithFlags(&g_cap_stream[k.dev], hipStreamNonBlocking));
+    hipStream_t cs = g_cap_stream[k.dev];
+    PCF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    SortArgs b = a;
+    b.stream = cs;
+    const int rc = dispatch(b, lay, ws, pol, has_pay, chain_levels(a.n, pol.lds_cap));
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &gr);
+    if (rc != PCF_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture", __LINE__);
+    GraphEntry ne = {};
+    ne.key = k;
+    const hipError_t ei = hipGraphInstantiate(&ne.exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate", __LINE__);
+    const hipError_t ev = hipEventCreateWithFlags(&ne.done, hipEventDisableTiming);
+    if (ev != hipSuccess) {
+      (void)hipGraphExecDestroy(ne.exec);
+      return hip_fail(ev, "hipEventCreate", __LINE__);
+    }
+    if (g_graphs.size() >= GRAPH_CACHE) {  // evict the least recently used
+      size_t v = 0;
+      for (size_t i = 1; i < g_graphs.size(); ++i)
+        if (g_graphs[i].tick < g_graphs[v].tick) v = i;
+      PCF_HIP(hipEventSynchronize(g_graphs[v].done));
+      (void)hipGraphExecDestroy(g_graphs[v].exec);
+      (void)hipEventDestroy(g_graphs[v].done);
+      g_graphs.erase(g_graphs.begin() + (long)v);
+    }
+    g_graphs.push_back(ne);
+    e = &g_graphs.back();
+    ++g_graph_captures;
+  } else {
+    ++g_graph_replays;
+  }
+  e->tick = ++g_graph_tick;
+  PCF_HIP(hipGraphLaunch(e->exec, a.stream));
+  PCF_HIP(hipEventRecord(e->done, a.stream));
+  if (a.d_status) return PCF_OK;
+  // no status word: wait and report the outcome
+  Ctl hc;
+  PCF_HIP(hipMemcpyAsync(&hc, ws + lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
+  PCF_HIP(hipStreamSynchronize(a.stream));
+  if (hc.status) return hc.status;
+  if (hc.overflow) return overflow_status(hc.overflow);
+  return PCF_OK;
+}
+
+int graph_stats(uint64_t* captures, uint64_t* replays, uint64_t* cached) {
+  std::lock_guard<std::mutex> g(g_graph_mu);
+  if (captures) *captures = g_graph_captures;
+  if (replays) *replays = g_graph_replays;
+  if (cached) *cached = g_graphs.size();
+  return PCF_OK;
+}
+
+int graph_clear() {
+  std::lock_guard<std::mutex> g(g_graph_mu);
+  for (auto& x : g_graphs) {
+    PCF_HIP(hipEventSynchronize(x.done));
+    (void)hipGraphExecDestroy(x.exec);
+    (void)hipEventDestroy(x.done);
+  }
+  g_graphs.clear();
+  return PCF_OK;
+}
+
 int run_sort(const SortArgs& a) {
   if (a.key_type != PCF_KEY_F64 && a.key_type != PCF_KEY_U64) return PCF_ERR_INVALID_ARGUMENT;
   if (a.n == 0) {
@@ -571,10 +729,10 @@ int run_sort(const SortArgs& a) {
     return PCF_ERR_OUT_OF_MEMORY;
   }
   int rc;
-  if (a.key_type == PCF_KEY_F64)
-    rc = has_pay ? run_typed<KT_F64, 1>(a, lay, ws, pol) : run_typed<KT_F64, 0>(a, lay, ws, pol);
+  if (!own && use_graph(a))
+    rc = run_graph(a, lay, ws, pol, has_pay);
   else
-    rc = has_pay ? run_typed<KT_U64, 1>(a, lay, ws, pol) : run_typed<KT_U64, 0>(a, lay, ws, pol);
+    rc = dispatch(a, lay, ws, pol, has_pay, 0);
   if (own) {
     hipError_t e = hipFreeAsync(ws, a.stream);
     if (e != hipSuccess && rc == PCF_OK) rc = hip_fail(e);
@@ -716,6 +874,12 @@ int pcf_sort_segmented(int key_type, const void* d_keys_in, void* d_keys_out,
   a.stream = reinterpret_cast<hipStream_t>(stream);
   return run_sort(a);
 }
+
+int pcf_graph_stats(uint64_t* captures, uint64_t* replays, uint64_t* cached) {
+  return graph_stats(captures, replays, cached);
+}
+
+int pcf_graph_clear(void) { return graph_clear(); }
 
 int pcf_level_trace(int key_type, const void* d_keys_in, const uint32_t* d_vals_in, size_t n,
                     uint64_t node_seed_v, uint32_t alpha, uint32_t beta, uint32_t gamma,

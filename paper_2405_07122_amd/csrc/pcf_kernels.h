@@ -24,6 +24,11 @@ struct RootArgs {
 
 __global__ void k_roots(Plan p, RootArgs a);
 __global__ void k_init(Plan p);
+// Publishes a call's outcome to the caller's device status word (when given)
+// and to Ctl::status: the data error, else PCF_ERR_OUT_OF_MEMORY for a
+// capacity overflow or nodes left at `check_level` (the end of a fixed chain;
+// -1: no check), else PCF_ERR_HIP for a failed internal range check.
+__global__ void k_finish(Plan p, int32_t* d_status, int check_level);
 
 struct LevelIO {
   void* dst_keys;       // where this level's scatter writes (absolute positions)

@@ -49,9 +49,13 @@
 namespace pcf {
 
 constexpr int ERR_INVALID_KEY = 2;  // PCF_ERR_INVALID_KEY
+constexpr int ERR_OUT_OF_MEMORY = 3;  // PCF_ERR_OUT_OF_MEMORY
+constexpr int ERR_HIP = 4;  // PCF_ERR_HIP
 
+// No data error and no overflow so far (status and overflow are the first
+// 8 bytes of the 256-byte aligned control block: one load reads both).
 __device__ __forceinline__ bool ctl_ok(const Ctl* c) {
-  return *reinterpret_cast<const volatile int32_t*>(&c->status) == 0;
+  return *reinterpret_cast<const volatile uint64_t*>(c) == 0ull;
 }
 
 __device__ __forceinline__ void flag_overflow(Ctl* c) { atomicOr(&c->overflow, OVF_CAPACITY); }
@@ -66,6 +70,17 @@ __device__ __forceinline__ void flag_internal(Ctl* c) { atomicOr(&c->overflow, O
 __global__ void k_init(Plan p) {
   uint32_t* w = reinterpret_cast<uint32_t*>(p.ctl);
   for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
+}
+
+__global__ void k_finish(Plan p, int32_t* d_status, int check_level) {
+  if (threadIdx.x != 0) return;
+  Ctl* c = p.ctl;
+  if (check_level >= 0 && check_level < MAX_LEVELS && c->lv[check_level].num_nodes != 0)
+    atomicOr(&c->overflow, OVF_CAPACITY);
+  int32_t s = c->status;
+  const uint32_t ovf = c->overflow;
+  if (s == 0 && ovf) s = (ovf & OVF_INTERNAL) ? ERR_HIP : ERR_OUT_OF_MEMORY;
+  if (d_status) *d_status = s;
 }
 
 // Creates the roots: one node (or one LDS item) per non-empty segment.  A

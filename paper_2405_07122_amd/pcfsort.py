@@ -37,7 +37,8 @@ EXPORTS = [
     "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
-    "pcf_profile_enable", "pcf_profile_read", "pcf_kernel_name",
+    "pcf_profile_enable", "pcf_profile_read", "pcf_kernel_name", "pcf_graph_stats",
+    "pcf_graph_clear",
 ]
 
 KERNEL_KINDS = ["setup", "range", "fit", "count", "colscan", "classify", "scatter", "lds_small",
@@ -134,6 +135,8 @@ def load(path: str = LIB_PATH):
         "pcf_profile_enable": (_INT, [_INT]),
         "pcf_profile_read": (_INT, [ctypes.POINTER(KernelStat), _INT]),
         "pcf_kernel_name": (ctypes.c_char_p, [_INT]),
+        "pcf_graph_stats": (_INT, [ctypes.POINTER(_U64)] * 3),
+        "pcf_graph_clear": (_INT, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -260,6 +263,18 @@ def pcf_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Te
                                   _ptr(offsets), nseg, keys.numel(), wp, wb, _ptr(d_status),
                                   _stream(stream)), "pcf_sort_segmented")
     return keys_out, vals_out
+
+
+def pcf_graph_stats() -> dict:
+    """Graph cache counters of the segmented path."""
+    c, r, h = _U64(), _U64(), _U64()
+    _check(load().pcf_graph_stats(ctypes.byref(c), ctypes.byref(r), ctypes.byref(h)),
+           "pcf_graph_stats")
+    return {"captures": c.value, "replays": r.value, "cached": h.value}
+
+
+def pcf_graph_clear() -> None:
+    _check(load().pcf_graph_clear(), "pcf_graph_clear")
 
 
 def pcf_level_trace(keys: torch.Tensor, alpha: int, beta: int, gamma: int, node_seed: int,

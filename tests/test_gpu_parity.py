@@ -199,3 +199,94 @@ def test_segmented_equals_per_array_plain(P):
         np.testing.assert_array_equal(gk[a:b], to_host(pk, np.float64))
         # the payload is the in-segment index, so it equals the argsort
         np.testing.assert_array_equal(gv[a:b], to_host(pi, np.uint32))
+
+
+def _segment_data(kind, seed):
+    """Same segment sizes as _segments, new contents per seed."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, m in enumerate(SEG_SIZES):
+        if kind == "f64":
+            parts.append(datagen.f64(datagen.F64_DISTS[(i + seed) % 6], m, seed * 100 + i))
+        else:
+            parts.append(datagen.u64(datagen.U64_KINDS[(i + seed) % 3], m, seed * 100 + i,
+                                     distinct=5000) if m else np.zeros(0, np.uint64))
+    vals = rng.integers(0, 2**32, sum(SEG_SIZES), dtype=np.uint64).astype(np.uint32)
+    return np.concatenate(parts), vals
+
+
+@pytest.mark.parametrize("kind", ["f64", "u64"])
+@pytest.mark.parametrize("payload", [False, True])
+def test_segmented_graph_replays(P, oracle, kind, payload):
+    """With a caller workspace the segmented call is captured once and replayed;
+    every replay reads the buffers' current contents and matches the oracle,
+    with unrelated eager work between replays, and a data error in one replay
+    does not leak into the next."""
+    import torch
+    banner(f"segmented graph replays {kind} payload={payload}")
+    dt = np.float64 if kind == "f64" else np.uint64
+    tdt = torch.float64 if kind == "f64" else torch.int64
+    offsets = np.zeros(len(SEG_SIZES) + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(SEG_SIZES)
+    n = int(offsets[-1])
+    d_keys = torch.empty(n, dtype=tdt, device="cuda")
+    d_vals = torch.empty(n, dtype=torch.int32, device="cuda") if payload else None
+    d_off = to_dev(offsets.view(np.int64))
+    k_out = torch.empty_like(d_keys)
+    v_out = torch.empty_like(d_vals) if payload else None
+    ws = P.workspace(P.KEY_F64 if kind == "f64" else P.KEY_U64, n, payload, len(SEG_SIZES))
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s0 = P.pcf_graph_stats()
+    for rep in range(5):
+        keys, vals = _segment_data(kind, 20 + rep)
+        bad = rep == 2 and kind == "f64"
+        if bad:
+            keys = keys.copy()
+            keys[int(offsets[5]) + 3] = np.nan
+        d_keys.copy_(to_dev(keys))
+        if payload:
+            d_vals.copy_(to_dev(vals))
+        P.pcf_sort_segmented(d_keys, d_off, d_vals, keys_out=k_out, vals_out=v_out, ws=ws,
+                             d_status=st)
+        # unrelated eager work on the same stream between replays
+        junk = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+        P.pcf_sort_f64(junk)
+        torch.cuda.synchronize()
+        code = int(st.cpu()[0])
+        if bad:
+            assert code == P.ERR_INVALID_KEY
+            continue
+        assert code == 0
+        ref_k, ref_v = oracle.sort_segmented(keys, offsets, vals if payload else None)
+        np.testing.assert_array_equal(to_host(k_out, dt), ref_k)
+        if payload:
+            np.testing.assert_array_equal(to_host(v_out, np.uint32), ref_v)
+    s1 = P.pcf_graph_stats()
+    assert s1["captures"] - s0["captures"] == 1
+    assert s1["replays"] - s0["replays"] == 4
+
+
+def test_segmented_graph_in_place_and_no_status(P, oracle):
+    """In-place replays (keys_in == keys_out) and the synchronous form without a
+    status word, which reports an invalid key through its return code."""
+    import torch
+    banner("segmented graph in place")
+    offsets = np.zeros(len(SEG_SIZES) + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(SEG_SIZES)
+    n = int(offsets[-1])
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    d_off = to_dev(offsets.view(np.int64))
+    ws = P.workspace(P.KEY_F64, n, False, len(SEG_SIZES))
+    for rep in range(3):
+        keys, _ = _segment_data("f64", 40 + rep)
+        d.copy_(to_dev(keys))
+        P.pcf_sort_segmented(d, d_off, None, keys_out=d, ws=ws)
+        ref_k, _ = oracle.sort_segmented(keys, offsets, None)
+        np.testing.assert_array_equal(to_host(d, np.float64), ref_k)
+    keys[17] = np.inf
+    d.copy_(to_dev(keys))
+    with pytest.raises(P.PcfError) as ei:
+        P.pcf_sort_segmented(d, d_off, None, keys_out=d, ws=ws)
+    assert ei.value.code == P.ERR_INVALID_KEY
+    P.pcf_graph_clear()
+    assert P.pcf_graph_stats()["cached"] == 0
