@@ -71,6 +71,67 @@ def cpu_baseline(x, sample: int):
                       f"single thread, {dt:.2f} s"}
 
 
+def batched_leg(P, reps: int, num: int):
+    """Segmented workload: `num` fp64 segments of floor(2^U[10,22]) keys (seed 10)
+    with a uint32 payload = in-segment index; the captured graph of one
+    pcf_sort_segmented call against a loop of plain pcf_argsort calls (one per
+    segment, same buffers).  Both outputs must agree bit for bit."""
+    import numpy as np
+    import torch
+
+    from paper_2405_07122_amd import datagen
+    keys, offsets, vals = datagen.segments(num=num)
+    n = int(offsets[-1])
+    log(f"batched: {num} segments, {n} keys")
+    dk = torch.from_numpy(keys).to("cuda")
+    dv = torch.from_numpy(vals.view(np.int32)).to("cuda")
+    doff = torch.from_numpy(offsets.view(np.int64)).to("cuda")
+    del keys, vals
+    ko = torch.empty_like(dk)
+    vo = torch.empty_like(dv)
+    ws = P.workspace(P.KEY_F64, n, True, num)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.pcf_sort_segmented(dk, doff, dv, keys_out=ko, vals_out=vo, ws=ws, d_status=st)  # capture
+    torch.cuda.synchronize()
+    if int(st.item()) != 0:
+        raise RuntimeError(f"segmented status {int(st.item())}")
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.pcf_sort_segmented(dk, doff, dv, keys_out=ko, vals_out=vo, ws=ws, d_status=st)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    # the plain path: one argsort per segment into the same output slices
+    ko2 = torch.empty_like(dk)
+    vo2 = torch.empty_like(dv)
+    off = offsets.tolist()
+
+    def plain():
+        for s in range(num):
+            a, b = off[s], off[s + 1]
+            if b > a:
+                P.pcf_argsort(dk[a:b], keys_out=ko2[a:b], idx_out=vo2[a:b], ws=ws)
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_reps = max(1, reps // 2)
+    for _ in range(plain_reps):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / plain_reps
+    same = bool(torch.equal(ko, ko2) and torch.equal(vo, vo2))
+    if not same:
+        raise RuntimeError("segmented output differs from the per-segment plain path")
+    g = P.pcf_graph_stats()
+    del dk, dv, ko, vo, ko2, vo2, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"{num} fp64 segments, sizes floor(2^U[10,22]), seed 10, uint32 "
+                        f"payload = in-segment index, {n} keys",
+            "keys": n, "graph_ms": t_graph * 1e3, "graph_keys_per_s": n / t_graph,
+            "plain_loop_ms": t_plain * 1e3, "plain_loop_keys_per_s": n / t_plain,
+            "speedup_vs_plain": t_plain / t_graph, "reps": reps, "bit_identical": same,
+            "graph_captures": g["captures"], "graph_replays": g["replays"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +142,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--argsort", action="store_true", help="also time argsort (untimed leg)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the segmented leg")
+    ap.add_argument("--batched-segments", type=int, default=2048)
+    ap.add_argument("--batched-reps", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of n fp64 keys first (reference for the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE scale)")
@@ -166,6 +230,11 @@ def main():
             pcfsort.pcf_argsort(dev[dists[k % len(dists)]], keys_out=out, idx_out=idx, ws=wsa)
         torch.cuda.synchronize()
         extra["argsort_keys_per_s"] = reps * n / (time.perf_counter() - ta)
+
+    if not args.no_batched:
+        del dev, out, ws
+        torch.cuda.empty_cache()
+        extra["batched"] = batched_leg(pcfsort, args.batched_reps, args.batched_segments)
 
     cpu = None
     if not args.no_cpu:
