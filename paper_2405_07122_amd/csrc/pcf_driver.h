@@ -42,6 +42,8 @@ struct SortArgs {
   uint32_t* vals_out;      // NULL: keys only
   int iota;
   const uint64_t* offsets; // device CSR offsets or NULL
+  const uint64_t* seg_src; // device array of per-segment key addresses (keys_in unused), or NULL
+  int no_graph;            // segmented: always launch eagerly
   uint32_t nseg;
   size_t n;
   void* ws;
@@ -61,6 +63,8 @@ struct SortArgs {
 };
 
 int run_sort(const SortArgs& a);
+// Exact workspace of one call (int_keys: argsort without a key output).
+size_t workspace_for(int key_type, size_t n, int has_pay, uint32_t nseg, int int_keys);
 int graph_stats(uint64_t* captures, uint64_t* replays, uint64_t* cached);
 int graph_clear();
 

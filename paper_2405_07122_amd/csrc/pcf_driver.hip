@@ -348,6 +348,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
 
   RootArgs ra = {};
   ra.keys = a.keys_in;
+  ra.seg_src = a.seg_src;
   ra.vals = a.vals_in;
   ra.offsets = a.offsets;
   ra.n = a.n;
@@ -606,7 +607,7 @@ static bool graphs_enabled() {
 }
 
 static bool use_graph(const SortArgs& a) {
-  if (!a.offsets || a.trace || !graphs_enabled()) return false;
+  if (!a.offsets || a.trace || a.no_graph || !graphs_enabled()) return false;
   std::lock_guard<std::mutex> g(g_prof_mu);
   return !g_prof_on;  // profiling records events per launch: eager path
 }
@@ -704,13 +705,19 @@ int graph_clear() {
   return PCF_OK;
 }
 
+size_t workspace_for(int key_type, size_t n, int has_pay, uint32_t nseg, int int_keys) {
+  (void)key_type;
+  return make_layout(n, has_pay, nseg ? nseg : 1, current_policy(), int_keys, 0, 0).total;
+}
+
 int run_sort(const SortArgs& a) {
   if (a.key_type != PCF_KEY_F64 && a.key_type != PCF_KEY_U64) return PCF_ERR_INVALID_ARGUMENT;
   if (a.n == 0) {
     if (a.d_status) PCF_HIP(hipMemsetAsync(a.d_status, 0, sizeof(int32_t), a.stream));
     return PCF_OK;
   }
-  if (!a.keys_in) return PCF_ERR_INVALID_ARGUMENT;
+  if (!a.keys_in && !a.seg_src) return PCF_ERR_INVALID_ARGUMENT;
+  if (a.seg_src && (!a.offsets || !a.keys_out)) return PCF_ERR_INVALID_ARGUMENT;
   if (a.n >= (1ull << 32)) return PCF_ERR_INVALID_ARGUMENT;
   const int has_pay = a.vals_out != nullptr;
   if (has_pay && !a.iota && !a.vals_in) return PCF_ERR_INVALID_ARGUMENT;

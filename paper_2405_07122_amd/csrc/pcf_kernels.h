@@ -11,6 +11,7 @@ namespace pcf {
 // offsets == NULL means one segment [0, n).
 struct RootArgs {
   const void* keys;
+  const uint64_t* seg_src;  // per-segment key addresses (device), or NULL: keys + offset
   const uint32_t* vals;
   const uint64_t* offsets;
   uint64_t n;

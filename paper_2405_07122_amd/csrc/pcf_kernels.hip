@@ -136,7 +136,8 @@ __global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
     const uint32_t t_i1 = tot;
     const uint32_t o_i2 = block_excl_scan<ROOT_NT>(item && icls == 2 ? 1u : 0u, red, tot);
     const uint32_t t_i2 = tot;
-    const char* kb = reinterpret_cast<const char*>(a.keys) + b0 * 8ull;
+    const char* kb = a.seg_src ? (s < a.nseg ? reinterpret_cast<const char*>(a.seg_src[s]) : nullptr)
+                               : reinterpret_cast<const char*>(a.keys) + b0 * 8ull;
     const uint32_t* vb = a.vals ? a.vals + b0 : nullptr;
     if (item) {
       const uint64_t idx = base[5 + icls] + (icls == 0 ? o_i0 : (icls == 1 ? o_i1 : o_i2));

@@ -334,3 +334,86 @@ def pcf_profile_read(reset: bool = False) -> dict:
     _check(load().pcf_profile_read(arr, int(reset)), "pcf_profile_read")
     return {KERNEL_KINDS[i]: {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
                               "keys": float(arr[i].keys)} for i in range(len(KERNEL_KINDS))}
+
+
+# ---- serving ------------------------------------------------------------------
+
+class _DevView:
+    """A device buffer owned by the server, exposed to torch without a copy."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
+                                         "version": 3, "strides": None}
+
+
+class Server:
+    """Continuous-batching sort server (pcf_serve_*).  submit() never blocks;
+    results stay in server memory until release()."""
+
+    def __init__(self, hbm_budget_bytes: int, max_streams: int = 2, max_batch_requests: int = 256,
+                 max_batch_keys: int = 1 << 28, device: int = 0):
+        lib = load()
+        cfg = ServeConfig(hbm_budget_bytes, max_streams, max_batch_requests, max_batch_keys, device,
+                          0)
+        h = ctypes.c_void_p()
+        _check(lib.pcf_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "pcf_serve_create")
+        self._h = h
+        self._inputs = {}
+
+    def submit(self, keys: torch.Tensor, argsort: bool = False) -> int:
+        """Returns a ticket; `keys` is kept alive until the request is released."""
+        _need_cuda(keys)
+        t = _U64()
+        _check(load().pcf_serve_submit(self._h, _key_type(keys), _ptr(keys), keys.numel(),
+                                       int(argsort), ctypes.byref(t)), "pcf_serve_submit")
+        self._inputs[t.value] = keys
+        return t.value
+
+    def _result(self, r: ServeResult, kt_dtype) -> dict:
+        out = {"n": int(r.n), "latency_ns": int(r.latency_ns), "queue_ns": int(r.queue_ns),
+               "status": int(r.status), "batch_requests": int(r.batch_requests),
+               "keys": None, "idx": None}
+        if r.n and r.d_keys_sorted:
+            ts = "<f8" if kt_dtype == torch.float64 else "<i8"
+            out["keys"] = torch.as_tensor(_DevView(r.d_keys_sorted, r.n, ts), device="cuda")
+        if r.n and r.d_idx:
+            out["idx"] = torch.as_tensor(_DevView(r.d_idx, r.n, "<i4"), device="cuda")
+        return out
+
+    def poll(self, ticket: int):
+        """None while pending, else the result dict (tensors view server memory)."""
+        r = ServeResult()
+        rc = load().pcf_serve_poll(self._h, ticket, ctypes.byref(r))
+        if rc == PENDING:
+            return None
+        _check(rc, "pcf_serve_poll")
+        return self._result(r, self._inputs[ticket].dtype)
+
+    def wait(self, ticket: int, timeout_ms: int = 60000):
+        r = ServeResult()
+        rc = load().pcf_serve_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
+        if rc == PENDING:
+            return None
+        _check(rc, "pcf_serve_wait")
+        return self._result(r, self._inputs[ticket].dtype)
+
+    def release(self, ticket: int) -> None:
+        _check(load().pcf_serve_release(self._h, ticket), "pcf_serve_release")
+        self._inputs.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(load().pcf_serve_get_stats(self._h, ctypes.byref(st)), "pcf_serve_get_stats")
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().pcf_serve_destroy(self._h), "pcf_serve_destroy")
+            self._h = None
+            self._inputs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
