@@ -132,6 +132,117 @@ def batched_leg(P, reps: int, num: int):
             "graph_captures": g["captures"], "graph_replays": g["replays"]}
 
 
+# fixed lower clips of the u64 request keys floor((x - L) * 2^32), per distribution
+U64_CLIP = {"uniform": 0.0, "normal": -8.0, "lognormal": 0.0, "exponential": 0.0, "chi2_4": 0.0,
+            "mix8": -200.0}
+
+
+def served_leg(P, dev: dict, rates, count: int, budget: int, streams: int):
+    """Open-loop serving: Poisson arrivals (seed 11) of sort requests with sizes
+    floor(2^U[12,26]), key type fp64 or u64 (u64 = floor((x - L) 2^32) of the
+    fp64 draw), distribution from the six arrays, each a slice at a seeded
+    offset of the resident 1e8-key arrays.  Latency = completion - scheduled
+    arrival.  The same trace then runs through the plain path: one call at a
+    time, FIFO, on one stream."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    from paper_2405_07122_amd import datagen
+    dists = list(dev)
+    pool_n = min(t.numel() for t in dev.values())
+    u64 = {d: torch.floor(torch.clamp(dev[d] - U64_CLIP[d], min=0.0) * 4294967296.0).to(torch.int64)
+           for d in dists}
+    maxn = 1 << 26
+    out_k = torch.empty(maxn, dtype=torch.float64, device="cuda")
+    ws = P.workspace(P.KEY_F64, maxn)
+    res = {}
+    for rate in rates:
+        trace = datagen.request_trace(rate, count, seed=11)
+        rng = np.random.default_rng(int(rate))
+        reqs = []
+        for (arr, n, kind, dist) in trace:
+            dist = dist if dist in dev else dists[0]
+            n = min(n, pool_n)
+            off = int(rng.integers(0, pool_n - n + 1))
+            src = (dev if kind == "f64" else u64)[dist][off:off + n]
+            reqs.append((arr, n, src))
+        keys_total = sum(r[1] for r in reqs)
+        # served
+        lat = []
+        batch_sizes = []
+        with P.Server(budget, max_streams=streams, max_batch_requests=256,
+                      max_batch_keys=1 << 28) as srv:
+            for (_, n, src) in reqs[:4]:  # warm-up outside the trace
+                t = srv.submit(src)
+                srv.wait(t)
+                srv.release(t)
+            torch.cuda.synchronize()
+            pending = collections.deque()
+            t0 = time.perf_counter()
+            i = 0
+            last_done = 0.0
+            while i < len(reqs) or pending:
+                now = time.perf_counter() - t0
+                while i < len(reqs) and reqs[i][0] <= now:
+                    t = srv.submit(reqs[i][2])
+                    pending.append((t, reqs[i][0], time.perf_counter() - t0))
+                    i += 1
+                progressed = False
+                for _ in range(min(len(pending), 64)):
+                    t, arr, sub = pending[0]
+                    st = srv.poll_status(t)
+                    if st is None:
+                        pending.rotate(-1)
+                        continue
+                    pending.popleft()
+                    status, lat_ns, bsz = st
+                    if status != 0:
+                        raise RuntimeError(f"served request failed with status {status}")
+                    done = sub + lat_ns * 1e-9
+                    last_done = max(last_done, done)
+                    lat.append(done - arr)
+                    batch_sizes.append(bsz)
+                    srv.release(t)
+                    progressed = True
+                if not progressed and i < len(reqs):
+                    time.sleep(min(5e-4, max(0.0, reqs[i][0] - (time.perf_counter() - t0))))
+            stats = srv.stats()
+        served_span = last_done - reqs[0][0]
+        # plain: FIFO, one call at a time on one stream
+        plat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (arr, n, src) in reqs:
+            now = time.perf_counter() - t0
+            if now < arr:
+                time.sleep(arr - now)
+            P.sort(src, out=out_k[:n].view(src.dtype), ws=ws)
+            torch.cuda.synchronize()
+            plat.append(time.perf_counter() - t0 - arr)
+        plain_span = time.perf_counter() - t0 - reqs[0][0]
+        lat = np.array(lat)
+        plat = np.array(plat)
+        res[str(rate)] = {
+            "requests": len(reqs), "keys": keys_total,
+            "served": {"keys_per_s": keys_total / served_span,
+                       "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                       "mean_batch_requests": float(np.mean(batch_sizes)),
+                       "batches": stats["batches"], "budget_high_water": stats["budget_high_water"]},
+            "plain_fifo": {"keys_per_s": keys_total / plain_span,
+                           "p50_ms": float(np.percentile(plat, 50) * 1e3),
+                           "p99_ms": float(np.percentile(plat, 99) * 1e3)},
+        }
+        log(f"served rate {rate}: {res[str(rate)]}")
+    del u64, out_k, ws
+    return {"workload": f"Poisson arrivals (seed 11), {count} requests per rate, sizes "
+                        f"floor(2^U[12,26]), fp64/u64 50/50 over six distributions, "
+                        f"budget {budget >> 30} GiB, {streams} streams",
+            "rates": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +254,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--argsort", action="store_true", help="also time argsort (untimed leg)")
     ap.add_argument("--no-batched", action="store_true", help="skip the segmented leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
+    ap.add_argument("--served-rates", default="200,1000,5000")
+    ap.add_argument("--served-count", type=int, default=2000)
+    ap.add_argument("--served-streams", type=int, default=4)
     ap.add_argument("--batched-segments", type=int, default=2048)
     ap.add_argument("--batched-reps", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
@@ -230,6 +345,10 @@ def main():
             pcfsort.pcf_argsort(dev[dists[k % len(dists)]], keys_out=out, idx_out=idx, ws=wsa)
         torch.cuda.synchronize()
         extra["argsort_keys_per_s"] = reps * n / (time.perf_counter() - ta)
+
+    if not args.no_served:
+        extra["served"] = served_leg(pcfsort, dev, [float(r) for r in args.served_rates.split(",")],
+                                     args.served_count, 64 << 30, args.served_streams)
 
     if not args.no_batched:
         del dev, out, ws

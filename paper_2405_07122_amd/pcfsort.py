@@ -389,6 +389,16 @@ class Server:
         _check(rc, "pcf_serve_poll")
         return self._result(r, self._inputs[ticket].dtype)
 
+    def poll_status(self, ticket: int):
+        """None while pending, else (status, latency_ns, batch_requests) without
+        touching the result memory."""
+        r = ServeResult()
+        rc = load().pcf_serve_poll(self._h, ticket, ctypes.byref(r))
+        if rc == PENDING:
+            return None
+        _check(rc, "pcf_serve_poll")
+        return int(r.status), int(r.latency_ns), int(r.batch_requests)
+
     def wait(self, ticket: int, timeout_ms: int = 60000):
         r = ServeResult()
         rc = load().pcf_serve_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
