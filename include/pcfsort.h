@@ -202,10 +202,24 @@ typedef struct {
 int pcf_get_policy(pcf_policy *out);
 int pcf_set_policy(const pcf_policy *p);
 
+/* The policy a call of n keys uses: the loaded tuning table's entry for
+ * (key_type, with_payload, n) if there is one, else the process-wide policy. */
+int pcf_policy_for(int key_type, size_t n, int with_payload, pcf_policy *out);
+
 /*
- * Autotuner: times candidate policies on synthetic arrays on the current
- * device (about a minute) and writes the best per size class as JSON to
- * out_json.  pcf_load_tuning reads such a file and installs it.
+ * Autotuner: on the current device, for four size classes ([0, 2^18),
+ * [2^18, 2^22), [2^22, 2^25), [2^25, 2^32) keys, timed at 2^16, 2^20, 2^23
+ * and 2^26 keys), times candidate policies (max_buckets, samples_per_bucket,
+ * bins_per_bucket, chunk_keys, target_child; coordinate descent from the
+ * process-wide policy, hipEvent-timed, median of repeats, summed over uniform,
+ * normal and lognormal synthetic arrays) and writes the winners as JSON to
+ * out_json (format "pcfsort-tuning-1").  Takes a few seconds and about
+ * 4.5 GB of device memory; does not change the active policy.
+ * pcf_load_tuning reads such a file, validates every entry (policy limits as
+ * pcf_set_policy, no overlapping classes of one kind) and installs it as the
+ * table, replacing any previous one; json_path NULL clears the table.
+ * A workspace sized before a table is loaded may be too small afterwards
+ * (the call then returns PCF_ERR_OUT_OF_MEMORY).
  */
 int pcf_autotune(int key_type, int with_payload, const char *out_json);
 int pcf_load_tuning(const char *json_path);

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/pcfsort.h"
 #include "pcf_device.h"
 
@@ -44,6 +46,7 @@ struct SortArgs {
   const uint64_t* offsets; // device CSR offsets or NULL
   const uint64_t* seg_src; // device array of per-segment key addresses (keys_in unused), or NULL
   int no_graph;            // segmented: always launch eagerly
+  const pcf_policy* pol_override;  // NULL: the tuned / default policy for n
   uint32_t nseg;
   size_t n;
   void* ws;
@@ -69,6 +72,18 @@ int graph_stats(uint64_t* captures, uint64_t* replays, uint64_t* cached);
 int graph_clear();
 
 pcf_policy current_policy();
+
+// One size class of a tuning table: arrays of min_n <= n < max_n keys of the
+// given type (with or without a payload) use `pol`.
+struct TuneEntry {
+  int key_type, with_payload;
+  uint64_t min_n, max_n;
+  pcf_policy pol;
+  double ms;  // measured time of the representative size
+};
+pcf_policy policy_for(int key_type, size_t n, int has_pay);
+void install_table(const std::vector<TuneEntry>& t);
+int check_policy(const pcf_policy& p);
 int device_cus();
 
 }  // namespace pcf

@@ -62,7 +62,24 @@ pcf_policy current_policy() {
   return g_pol;
 }
 
-static int check_policy(const pcf_policy& p) {
+// Tuned policies per size class (pcf_load_tuning); sizes no entry covers use
+// g_pol.
+static std::vector<TuneEntry> g_table;
+
+pcf_policy policy_for(int key_type, size_t n, int has_pay) {
+  std::lock_guard<std::mutex> g(g_pol_mu);
+  for (const TuneEntry& e : g_table)
+    if (e.key_type == key_type && e.with_payload == (has_pay ? 1 : 0) && n >= e.min_n && n < e.max_n)
+      return e.pol;
+  return g_pol;
+}
+
+void install_table(const std::vector<TuneEntry>& t) {
+  std::lock_guard<std::mutex> g(g_pol_mu);
+  g_table = t;
+}
+
+int check_policy(const pcf_policy& p) {
   if (p.max_buckets < 2 || p.max_buckets > MAX_NB || (p.max_buckets & (p.max_buckets - 1)))
     return PCF_ERR_INVALID_ARGUMENT;
   if (p.target_child < 16 || p.bins_per_bucket < 1 || p.max_bins < 2 || p.max_bins > MAX_BINS)
@@ -706,8 +723,8 @@ int graph_clear() {
 }
 
 size_t workspace_for(int key_type, size_t n, int has_pay, uint32_t nseg, int int_keys) {
-  (void)key_type;
-  return make_layout(n, has_pay, nseg ? nseg : 1, current_policy(), int_keys, 0, 0).total;
+  return make_layout(n, has_pay, nseg ? nseg : 1, policy_for(key_type, n, has_pay), int_keys, 0, 0)
+      .total;
 }
 
 int run_sort(const SortArgs& a) {
@@ -722,7 +739,7 @@ int run_sort(const SortArgs& a) {
   const int has_pay = a.vals_out != nullptr;
   if (has_pay && !a.iota && !a.vals_in) return PCF_ERR_INVALID_ARGUMENT;
   if (!has_pay && !a.keys_out) return PCF_ERR_INVALID_ARGUMENT;
-  const pcf_policy pol = current_policy();
+  const pcf_policy pol = a.pol_override ? *a.pol_override : policy_for(a.key_type, a.n, has_pay);
   int r = set_attrs();
   if (r != PCF_OK) return r;
   const Layout lay = make_layout(a.n, has_pay, a.nseg, pol, a.keys_out == nullptr,
@@ -773,8 +790,7 @@ int pcf_last_hip_error(void) { return g_last_hip_error; }
 const char* pcf_version(void) { return "pcfsort 0.1 (gfx950)"; }
 
 size_t pcf_workspace_bytes(int key_type, size_t n, int with_payload, uint32_t num_segments) {
-  (void)key_type;
-  const pcf_policy pol = current_policy();
+  const pcf_policy pol = policy_for(key_type, n, with_payload);
   // argsort may need internal keys: include them
   return make_layout(n, with_payload, num_segments ? num_segments : 1, pol, with_payload, 0, 0)
       .total;
@@ -803,6 +819,12 @@ const char* pcf_kernel_name(int kind) {
 int pcf_get_policy(pcf_policy* out) {
   if (!out) return PCF_ERR_INVALID_ARGUMENT;
   *out = current_policy();
+  return PCF_OK;
+}
+
+int pcf_policy_for(int key_type, size_t n, int with_payload, pcf_policy* out) {
+  if (!out || (key_type != PCF_KEY_F64 && key_type != PCF_KEY_U64)) return PCF_ERR_INVALID_ARGUMENT;
+  *out = policy_for(key_type, n, with_payload);
   return PCF_OK;
 }
 

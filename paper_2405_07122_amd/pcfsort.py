@@ -38,7 +38,7 @@ EXPORTS = [
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
     "pcf_profile_enable", "pcf_profile_read", "pcf_kernel_name", "pcf_graph_stats",
-    "pcf_graph_clear",
+    "pcf_graph_clear", "pcf_policy_for",
 ]
 
 KERNEL_KINDS = ["setup", "range", "fit", "count", "colscan", "classify", "scatter", "lds_small",
@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
         "pcf_kernel_name": (ctypes.c_char_p, [_INT]),
         "pcf_graph_stats": (_INT, [ctypes.POINTER(_U64)] * 3),
         "pcf_graph_clear": (_INT, []),
+        "pcf_policy_for": (_INT, [_INT, _SZ, _INT, ctypes.POINTER(Policy)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -320,8 +321,15 @@ def pcf_autotune(key_type: int, with_payload: bool, out_json: str) -> None:
     _check(load().pcf_autotune(key_type, int(with_payload), out_json.encode()), "pcf_autotune")
 
 
-def pcf_load_tuning(path: str) -> None:
-    _check(load().pcf_load_tuning(path.encode()), "pcf_load_tuning")
+def pcf_load_tuning(path: str | None) -> None:
+    """Installs a tuning table; None clears it."""
+    _check(load().pcf_load_tuning(path.encode() if path is not None else None), "pcf_load_tuning")
+
+
+def policy_for(key_type: int, n: int, with_payload: bool = False) -> dict:
+    p = Policy()
+    _check(load().pcf_policy_for(key_type, n, int(with_payload), ctypes.byref(p)), "pcf_policy_for")
+    return p.as_dict()
 
 
 def pcf_profile_enable(on: bool = True) -> None:
