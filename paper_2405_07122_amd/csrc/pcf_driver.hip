@@ -495,13 +495,13 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   // finish every small array inside LDS
   PCF_MARK(PCF_K_LDS_SMALL, 0,
            hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), dim3(cus * 4),
-                              dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>), st,
+                              dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), st,
                               p, 0));
   PCF_MARK(PCF_K_LDS_BIG, 0, {
     hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>), dim3(cus * 2),
-                       dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT>), st, p, 1);
+                       dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>), st, p, 1);
     hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), dim3(cus), dim3(K5_BIG_NT),
-                       sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>), st, p, 2);
+                       sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), st, p, 2);
   });
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status,
                      fixed_levels > 0 ? fixed_levels : -1);
@@ -536,13 +536,13 @@ template <int KT, int PAY>
 static int set_attrs_typed() {
   int r;
   if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
-                     sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT>))) != PCF_OK)
+                     sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>))) != PCF_OK)
     return r;
   if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
-                     sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT>))) != PCF_OK)
+                     sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>))) != PCF_OK)
     return r;
   if ((r = allow_lds(reinterpret_cast<const void*>(&k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
-                     sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT>))) != PCF_OK)
+                     sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>))) != PCF_OK)
     return r;
   const size_t sc_max = 160 * 1024 - 1024;  // scatter launches stay below this
   if (PAY) {

@@ -99,12 +99,12 @@ struct K5Cfg {
   static constexpr uint32_t SMAX = CAP / 16 + 8;  // ranges of >= tau (>= 16) keys
 };
 
-template <int KT, int CAP, int NT>
+template <int KT, int CAP, int NT, int PAY>
 struct K5Smem {
   uint64_t key[CAP];      // key images
-  uint16_t pos[CAP];      // position inside the item
   uint32_t seg[CAP];      // final segment: start | end << 16
-  uint32_t cnt[CAP + 2];  // bin counts, then bin starts
+  uint32_t cnt[CAP + 4];  // bin counts, then bin starts; cnt[CAP] = keys
+  uint16_t pos[PAY ? CAP : 2];  // position inside the item (ties, payload)
   uint32_t stk[K5Cfg<CAP>::SMAX][3];  // start, end, depth | fail << 31
   uint64_t red64[2 * NT / 64];
   uint32_t red[NT / 64 + 1];

@@ -1171,45 +1171,66 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
 // ---------------------------------------------------------------------------
 // Algorithm 1 inside LDS.  Every level trains the PCF on all m keys of its
 // array (alpha = m: Sec. 3.2 allows training on all elements) with beta = m
-// equal-width bins and gamma = alpha, so the bucket of a key,
-// floor(b_{i(x)} gamma / alpha) = b_{i(x)}, is its bin: buckets hold about one
-// key.  Buckets below tau get a counting rank, buckets of tau keys or more
-// recurse, failed buckets (>= delta = floor(m^{3/4})) get the standard sort
-// (in-LDS bitonic).  Ties are ordered by the key's position in the item,
-// which is its input order whenever a payload makes order observable (the
-// global scatters before this one are then stable).
-template <int KT, int CAP, int NT>
-__device__ void k5_bitonic(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e) {
+// equal-width bins, the top bin folded into bin m - 1, and gamma = alpha, so
+// the bucket of a key, floor(b_{i(x)} gamma / alpha) = b_{i(x)}, is its bin:
+// buckets hold about one key.  Buckets below tau get a counting rank, buckets
+// of tau keys or more recurse, failed buckets (>= delta = floor(m^{3/4})) get
+// the standard sort (in-LDS bitonic).  Ties are ordered by the key's position
+// in the item when a payload makes order observable (the global scatters
+// before this one are then stable); keys alone break ties by LDS index.
+//
+// The first level of an item runs from registers: keys are loaded once
+// (coalesced), bucketed with LDS-atomic ranks, and written to LDS already in
+// bin order, so an item whose bins all stay below tau costs five barriers.
+
+// Exact floor(n^{3/4}) for the failure test of the (rare) big bins: an fp64
+// estimate through two square roots, corrected with exact integer steps.
+__device__ __forceinline__ uint32_t k5_root34(uint32_t n) {
+  const double m = (double)n;
+  uint64_t r = (uint64_t)sqrt(sqrt(m * m * m));
+  auto le = [&](uint64_t x) {  // x^4 <= n^3 (both below 2^128: compare as 128-bit)
+    const uint64_t x2 = x * x, n2 = (uint64_t)n * n;
+    const uint64_t ah = __umul64hi(x2, x2), al = x2 * x2;
+    const uint64_t bh = __umul64hi(n2, (uint64_t)n), bl = n2 * (uint64_t)n;
+    return ah < bh || (ah == bh && al <= bl);
+  };
+  while (r > 0 && !le(r)) --r;
+  while (le(r + 1)) ++r;
+  return (uint32_t)r;
+}
+
+template <int KT, int CAP, int NT, int PAY>
+__device__ void k5_bitonic(K5Smem<KT, CAP, NT, PAY>& sm, uint32_t s, uint32_t e) {
   const uint32_t n = e - s;
   uint32_t P = 1;
   while (P < n) P <<= 1;
+  auto cmpswap = [&](uint32_t i, uint32_t j) {
+    const uint64_t ki = sm.key[s + i], kj = sm.key[s + j];
+    bool sw = kj < ki;
+    if (PAY) sw = sw || (kj == ki && sm.pos[s + j] < sm.pos[s + i]);
+    if (sw) {
+      sm.key[s + i] = kj;
+      sm.key[s + j] = ki;
+      if (PAY) {
+        const uint16_t pi = sm.pos[s + i];
+        sm.pos[s + i] = sm.pos[s + j];
+        sm.pos[s + j] = pi;
+      }
+    }
+  };
   for (uint32_t k = 2; k <= P; k <<= 1) {
     const uint32_t hk = k >> 1;
     for (uint32_t t = threadIdx.x; t < P / 2; t += NT) {
       const uint32_t blk = t / hk, o = t % hk;
       const uint32_t i = blk * k + o, j = blk * k + k - 1 - o;
-      if (j < n) {
-        const uint64_t ki = sm.key[s + i], kj = sm.key[s + j];
-        const uint16_t pi = sm.pos[s + i], pj = sm.pos[s + j];
-        if (kj < ki || (kj == ki && pj < pi)) {
-          sm.key[s + i] = kj; sm.key[s + j] = ki;
-          sm.pos[s + i] = pj; sm.pos[s + j] = pi;
-        }
-      }
+      if (j < n) cmpswap(i, j);
     }
     __syncthreads();
     for (uint32_t d = hk >> 1; d >= 1; d >>= 1) {
       for (uint32_t t = threadIdx.x; t < P / 2; t += NT) {
         const uint32_t blk = t / d, o = t % d;
         const uint32_t i = blk * 2 * d + o, j = i + d;
-        if (j < n) {
-          const uint64_t ki = sm.key[s + i], kj = sm.key[s + j];
-          const uint16_t pi = sm.pos[s + i], pj = sm.pos[s + j];
-          if (kj < ki || (kj == ki && pj < pi)) {
-            sm.key[s + i] = kj; sm.key[s + j] = ki;
-            sm.pos[s + i] = pj; sm.pos[s + j] = pi;
-          }
-        }
+        if (j < n) cmpswap(i, j);
       }
       __syncthreads();
     }
@@ -1218,91 +1239,145 @@ __device__ void k5_bitonic(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e) {
   __syncthreads();
 }
 
+// Exclusive scan, in place, of the bin counts cnt[0..CAP) of a level on the
+// LDS range [s, s + n) (bins at or beyond n are zero); cnt[CAP] = n.  Bins of
+// tau keys or more are pushed on the range stack, flagged as failed when they
+// hold delta = floor(n^{3/4}) keys or more.  Two barriers.
+template <int KT, int CAP, int NT, int PAY>
+__device__ __forceinline__ void k5_scan_bins(K5Smem<KT, CAP, NT, PAY>& sm, uint32_t s, uint32_t n,
+                                             uint32_t depth, uint32_t tau) {
+  constexpr int EC = CAP / NT;
+  static_assert(EC % 4 == 0, "bin runs are read as uint4");
+  const int l = lane_id(), w = wave_id();
+  uint4* p4 = reinterpret_cast<uint4*>(sm.cnt + threadIdx.x * EC);
+  uint32_t c[EC];
+#pragma unroll
+  for (int j = 0; j < EC / 4; ++j) {
+    const uint4 v = p4[j];
+    c[4 * j] = v.x;
+    c[4 * j + 1] = v.y;
+    c[4 * j + 2] = v.z;
+    c[4 * j + 3] = v.w;
+  }
+  uint32_t sum = 0;
+  bool big = false;
+#pragma unroll
+  for (int j = 0; j < EC; ++j) {
+    sum += c[j];
+    big |= c[j] >= tau;
+  }
+  const uint32_t incl = wave_incl_scan(sum);
+  if (l == 63) sm.red[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i)
+    if (i < w) run += sm.red[i];
+  uint32_t st[EC];
+#pragma unroll
+  for (int j = 0; j < EC; ++j) {
+    st[j] = run;
+    run += c[j];
+  }
+#pragma unroll
+  for (int j = 0; j < EC / 4; ++j)
+    p4[j] = make_uint4(st[4 * j], st[4 * j + 1], st[4 * j + 2], st[4 * j + 3]);
+  if (big) {  // rare: a bin of at least tau keys
+    const uint32_t delta = k5_root34(n);
+#pragma unroll
+    for (int j = 0; j < EC; ++j) {
+      if (c[j] >= tau) {
+        const uint32_t slot = atomicAdd(&sm.nstk, 1u);
+        if (slot < K5Cfg<CAP>::SMAX) {
+          sm.stk[slot][0] = s + st[j];
+          sm.stk[slot][1] = s + st[j] + c[j];
+          sm.stk[slot][2] = (depth + 1) | (c[j] >= delta ? 0x80000000u : 0u);
+        } else {
+          sm.flag = 1;  // cannot happen: ranges of >= tau keys are disjoint
+        }
+      }
+    }
+  }
+  if (threadIdx.x == 0) sm.cnt[CAP] = n;
+  __syncthreads();
+}
+
 // One PCF level on the LDS range [s, e) (a node of depth `depth`) with all of
 // its keys as the training set and one bin per key.
-template <int KT, int CAP, int NT>
-__device__ void k5_level(K5Smem<KT, CAP, NT>& sm, uint32_t s, uint32_t e, uint32_t depth,
+template <int KT, int CAP, int NT, int PAY>
+__device__ void k5_level(K5Smem<KT, CAP, NT, PAY>& sm, uint32_t s, uint32_t e, uint32_t depth,
                          uint64_t lo, uint64_t hi, uint32_t tau) {
   constexpr int EPT = (CAP + NT - 1) / NT;
+  constexpr int EC = CAP / NT;
   const uint32_t n = e - s;
-  const uint32_t beta = n, delta = root34(n);
   BinFn f;
-  if (!bin_setup<KT>(f, lo, hi, beta)) {
-    k5_bitonic<KT, CAP, NT>(sm, s, e);
+  if (!bin_setup<KT>(f, lo, hi, n)) {
+    k5_bitonic<KT, CAP, NT, PAY>(sm, s, e);
     return;
   }
-  for (uint32_t i = threadIdx.x; i <= beta + 1; i += NT) sm.cnt[i] = 0u;
+  uint4* p4 = reinterpret_cast<uint4*>(sm.cnt + threadIdx.x * EC);
+#pragma unroll
+  for (int j = 0; j < EC / 4; ++j) p4[j] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   uint64_t kk[EPT];
-  uint32_t pb[EPT];  // pos | bin << 16
-  uint32_t rk[EPT];
+  uint32_t bp[EPT];  // bin | rank << 16 (both below 2^16)
+  uint16_t ps[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const uint32_t i = s + threadIdx.x + k * NT;
     if (i < e) {
       kk[k] = sm.key[i];
-      const uint32_t b = bin_of<KT>(f, bits_of_img<KT>(kk[k]));
-      pb[k] = (uint32_t)sm.pos[i] | (b << 16);
-      rk[k] = atomicAdd(&sm.cnt[b], 1u);
+      if (PAY) ps[k] = sm.pos[i];
+      uint32_t b = bin_of<KT>(f, bits_of_img<KT>(kk[k]));
+      b = b < n - 1 ? b : n - 1;
+      bp[k] = b | (atomicAdd(&sm.cnt[b], 1u) << 16);
     }
   }
   __syncthreads();
-  block_scan_array<NT, false>(sm.cnt, beta + 1, sm.red);
-  if (threadIdx.x == 0) sm.cnt[beta + 1] = n;
-  __syncthreads();
+  k5_scan_bins<KT, CAP, NT, PAY>(sm, s, n, depth, tau);
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const uint32_t i = s + threadIdx.x + k * NT;
     if (i < e) {
-      const uint32_t b = pb[k] >> 16;
+      const uint32_t b = bp[k] & 0xffffu;
       const uint32_t a = sm.cnt[b], z = sm.cnt[b + 1];
-      const uint32_t d = s + a + rk[k];
+      const uint32_t d = s + a + (bp[k] >> 16);
       if (d >= e) continue;  // range check: cannot happen for consistent counts
       sm.key[d] = kk[k];
-      sm.pos[d] = (uint16_t)(pb[k] & 0xffffu);
+      if (PAY) sm.pos[d] = ps[k];
       sm.seg[d] = (s + a) | ((s + z) << 16);
-    }
-  }
-  // bins of at least tau keys need more work: recursion, or the standard sort
-  // when they failed (>= delta)
-  for (uint32_t q = threadIdx.x; q <= beta; q += NT) {
-    const uint32_t a = sm.cnt[q], b = sm.cnt[q + 1];
-    if (b - a >= tau) {
-      const uint32_t slot = atomicAdd(&sm.nstk, 1u);
-      if (slot < K5Cfg<CAP>::SMAX) {
-        sm.stk[slot][0] = s + a;
-        sm.stk[slot][1] = s + b;
-        sm.stk[slot][2] = (depth + 1) | ((b - a >= delta) ? 0x80000000u : 0u);
-      } else {
-        sm.flag = 1;  // cannot happen: ranges of >= tau keys are disjoint
-      }
     }
   }
   __syncthreads();
 }
 
 // Occupancy targets in waves per SIMD: 4 workgroups of 4 waves per CU for the
-// 2048-key class, 2 for 4096, 1 workgroup of 8 waves for 8192 (what their LDS
-// allows).
-template <int CAP>
+// 2048-key class (3 with a payload, whose registers need more room), 2 for
+// 4096, 1 workgroup of 8 waves for 8192 (what their LDS allows).
+template <int CAP, int PAY>
 struct K5Occ {
-  static constexpr int v = CAP <= 2048 ? 4 : 2;
+  static constexpr int v = CAP <= 2048 ? (PAY ? 3 : 4) : 2;
 };
 
 template <int KT, int CAP, int NT, int PAY>
-__global__ __launch_bounds__(NT, K5Occ<CAP>::v) void k_lds_sort(Plan p, int cls) {
+__global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, int cls) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  K5Smem<KT, CAP, NT>& sm = *reinterpret_cast<K5Smem<KT, CAP, NT>*>(lds_raw);
-  constexpr int EPT = (CAP + NT - 1) / NT;
+  K5Smem<KT, CAP, NT, PAY>& sm = *reinterpret_cast<K5Smem<KT, CAP, NT, PAY>*>(lds_raw);
+  constexpr int EPT = CAP / NT;
+  constexpr int NW = NT / 64;
   Ctl* c = p.ctl;
+  // the status is fixed while this kernel runs, except for invalid root keys
+  // found here, which concern only their own item
+  if (!ctl_ok(c)) return;
   const uint32_t total = c->item_count[cls] < p.cap_items[cls] ? c->item_count[cls]
                                                                 : p.cap_items[cls];
   const uint32_t tau = p.pol.tau;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
+  const int l = lane_id(), w = wave_id();
   unsigned long long done_keys = 0;
   // static assignment of items to workgroups (a shared work counter would be
-  // a same-address atomic per item); the next item's keys are prefetched
-  // into registers while this one is sorted
+  // a same-address atomic per item); with PCF_K5_PREFETCH the next item's
+  // keys are loaded into registers while this one is sorted
   uint64_t pre[EPT];
   if (PCF_K5_PREFETCH && blockIdx.x < total) {
     const Item it0 = p.items[cls][blockIdx.x];
@@ -1314,113 +1389,186 @@ __global__ __launch_bounds__(NT, K5Occ<CAP>::v) void k_lds_sort(Plan p, int cls)
     }
   }
   for (uint32_t ii = blockIdx.x; ii < total; ii += gridDim.x) {
-    if (threadIdx.x == 0) sm.sh[3] = ctl_ok(c) ? 1u : 0u;
-    __syncthreads();
-    const bool go = sm.sh[3] != 0;
-    __syncthreads();
-    if (!go) break;
     const Item it = p.items[cls][ii];
     const uint32_t m = it.len;
     done_keys += m;
-    if (!PCF_K5_PREFETCH) {
+    uint64_t kk[EPT];
+    if (PCF_K5_PREFETCH) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) kk[k] = pre[k];
+      const uint32_t nii = ii + gridDim.x;
+      if (nii < total) {
+        const Item nit = p.items[cls][nii];
+        const uint64_t* s1 = reinterpret_cast<const uint64_t*>(nit.src);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const uint32_t i = threadIdx.x + k * NT;
+          pre[k] = i < nit.len ? __builtin_nontemporal_load(s1 + i) : 0ull;
+        }
+      }
+    } else {
       const uint64_t* s0 = reinterpret_cast<const uint64_t*>(it.src);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        pre[k] = i < m ? s0[i] : 0ull;
+        kk[k] = i < m ? __builtin_nontemporal_load(s0 + i) : 0ull;
       }
     }
-    // keys to LDS, validate (roots), range
+    // validate (roots), images, range; clear the bins
     uint64_t lo = ~0ull, hi = 0ull;
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const uint32_t i = threadIdx.x + k * NT;
       if (i < m) {
-        const uint64_t bits = pre[k];
-        if (KT == KT_F64 && (it.flags & IF_ROOT)) bad |= !f64_bits_valid(bits);
-        const uint64_t im = img_of<KT>(bits);
-        sm.key[i] = im;
-        sm.pos[i] = (uint16_t)i;
-        sm.seg[i] = 0u | (m << 16);
-        lo = im < lo ? im : lo;
-        hi = im > hi ? im : hi;
+        if (KT == KT_F64 && (it.flags & IF_ROOT)) bad |= !f64_bits_valid(kk[k]);
+        kk[k] = img_of<KT>(kk[k]);
+        lo = kk[k] < lo ? kk[k] : lo;
+        hi = kk[k] > hi ? kk[k] : hi;
       }
     }
-    const uint32_t nii = ii + gridDim.x;
-    if (PCF_K5_PREFETCH && nii < total) {
-      const Item nit = p.items[cls][nii];
-      const uint64_t* s1 = reinterpret_cast<const uint64_t*>(nit.src);
+    {
+      uint4* p4 = reinterpret_cast<uint4*>(sm.cnt + threadIdx.x * EPT);
+#pragma unroll
+      for (int j = 0; j < EPT / 4; ++j) p4[j] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    lo = wave_min_u64(lo);
+    hi = wave_max_u64(hi);
+    const bool wbad = __ballot(bad) != 0ull;
+    if (l == 0) {
+      sm.red64[w] = lo;
+      sm.red64[NW + w] = hi;
+      sm.red[NW] = 0u;
+    }
+    if (threadIdx.x == 0) {
+      sm.nstk = 0;
+      sm.flag = 0;
+    }
+    __syncthreads();
+    if (wbad && l == 0) sm.red[NW] = 1u;  // read after the next barrier
+    lo = sm.red64[0];
+    hi = sm.red64[NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+      lo = sm.red64[i] < lo ? sm.red64[i] : lo;
+      hi = sm.red64[NW + i] > hi ? sm.red64[NW + i] : hi;
+    }
+    uint64_t* ok = ok_ + it.off;
+    if (lo == hi && KT == KT_U64) {
+      // single-valued: input order is the answer (a u64 range cannot be bad)
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        pre[k] = i < nit.len ? __builtin_nontemporal_load(s1 + i) : 0ull;
+        if (i < m) {
+          ok[i] = bits_of_img<KT>(kk[k]);
+          if (PAY) p.out_vals[it.off + i] = it.vsrc ? it.vsrc[i] : (uint32_t)it.rel + i;
+        }
       }
-    }
-    if (threadIdx.x == 0) {
-      sm.flag = 0;
-      sm.nstk = 0;
-    }
-    __syncthreads();
-    if (bad) sm.flag = 2;
-    block_minmax_u64<NT>(lo, hi, sm.red64);
-    if (sm.flag == 2) {
-      if (threadIdx.x == 0) atomicMax(&c->status, ERR_INVALID_KEY);
-      __syncthreads();
+      __syncthreads();  // the range was read from red64, which the next item rewrites
       continue;
     }
-    if (lo == hi) {
-      // single-valued: input order is the answer
-      for (uint32_t i = threadIdx.x; i < m; i += NT) sm.seg[i] = i | ((i + 1) << 16);
-      __syncthreads();
-    } else if (it.flags & IF_STD) {
-      k5_bitonic<KT, CAP, NT>(sm, 0, m);
-    } else if (m >= tau) {
-      k5_level<KT, CAP, NT>(sm, 0, m, it.depth, lo, hi, tau);
-      // ranges still at or above tau: recurse (or standard sort if failed)
-      while (sm.nstk != 0) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          const uint32_t k = sm.nstk < K5Cfg<CAP>::SMAX ? sm.nstk : K5Cfg<CAP>::SMAX;
-          if (k > 0) {
-            sm.sh[0] = sm.stk[k - 1][0];
-            sm.sh[1] = sm.stk[k - 1][1];
-            sm.sh[2] = sm.stk[k - 1][2];
-            sm.sh[3] = 1;
-            sm.nstk = k - 1;
-          } else {
-            sm.sh[3] = 0;
-          }
-        }
-        __syncthreads();
-        if (!sm.sh[3]) break;
-        const uint32_t rs = sm.sh[0], re = sm.sh[1];
-        const uint32_t rdepth = sm.sh[2] & 0x7fffffffu;
-        const bool rfail = (sm.sh[2] >> 31) != 0;
-        uint64_t rlo = ~0ull, rhi = 0ull;
-        for (uint32_t i = rs + threadIdx.x; i < re; i += NT) {
-          const uint64_t im = sm.key[i];
-          rlo = im < rlo ? im : rlo;
-          rhi = im > rhi ? im : rhi;
-        }
-        block_minmax_u64<NT>(rlo, rhi, sm.red64);
-        if (rlo == rhi) {
-          // equal keys: order them by position (the standard sort does it in
-          // O(m log^2 m); a counting rank would be quadratic)
-          k5_bitonic<KT, CAP, NT>(sm, rs, re);
-        } else if (rfail) {
-          k5_bitonic<KT, CAP, NT>(sm, rs, re);
-        } else {
-          k5_level<KT, CAP, NT>(sm, rs, re, rdepth, rlo, rhi, tau);
+    BinFn f;
+    const bool fast = m >= tau && lo != hi && !(it.flags & IF_STD) && bin_setup<KT>(f, lo, hi, m);
+    if (fast) {
+      // first level from registers: bin, rank inside the bin
+      uint32_t bp[EPT];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        if (i < m) {
+          uint32_t b = bin_of<KT>(f, bits_of_img<KT>(kk[k]));
+          b = b < m - 1 ? b : m - 1;
+          bp[k] = b | (atomicAdd(&sm.cnt[b], 1u) << 16);
         }
       }
+      __syncthreads();
+      if (sm.red[NW]) {  // invalid key in a root item
+        if (threadIdx.x == 0) atomicMax(&c->status, ERR_INVALID_KEY);
+        __syncthreads();
+        continue;
+      }
+      k5_scan_bins<KT, CAP, NT, PAY>(sm, 0, m, it.depth, tau);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        if (i < m) {
+          const uint32_t b = bp[k] & 0xffffu;
+          const uint32_t a = sm.cnt[b], z = sm.cnt[b + 1];
+          const uint32_t d = a + (bp[k] >> 16);
+          if (d >= m) continue;  // range check: cannot happen for consistent counts
+          sm.key[d] = kk[k];
+          if (PAY) sm.pos[d] = (uint16_t)i;
+          sm.seg[d] = a | (z << 16);
+        }
+      }
+      __syncthreads();
+    } else {
+      // standard sort (tiny, failed or unbucketable arrays) or, for fp64,
+      // a single value: everything goes through LDS; a range that needs the
+      // standard sort goes on the stack as a failed range
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const uint32_t i = threadIdx.x + k * NT;
+        if (i < m) {
+          sm.key[i] = kk[k];
+          if (PAY) sm.pos[i] = (uint16_t)i;
+          sm.seg[i] = lo == hi ? (i | ((i + 1) << 16)) : (m << 16);
+        }
+      }
+      if (threadIdx.x == 0 && lo != hi && m >= tau) {
+        sm.stk[0][0] = 0;
+        sm.stk[0][1] = m;
+        sm.stk[0][2] = (uint32_t)it.depth | 0x80000000u;
+        sm.nstk = 1;
+      }
+      __syncthreads();
+      if (sm.red[NW]) {
+        if (threadIdx.x == 0) atomicMax(&c->status, ERR_INVALID_KEY);
+        __syncthreads();
+        continue;
+      }
     }
-    __syncthreads();
-    // counting rank inside final segments.  With a payload, all reads (LDS
-    // keys and the payload, which may live in the very range being written)
-    // happen before a barrier and all writes after it.
+    // ranges still at or above tau: recurse (or standard sort if failed)
+    while (sm.nstk != 0) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t k = sm.nstk < K5Cfg<CAP>::SMAX ? sm.nstk : K5Cfg<CAP>::SMAX;
+        if (k > 0) {
+          sm.sh[0] = sm.stk[k - 1][0];
+          sm.sh[1] = sm.stk[k - 1][1];
+          sm.sh[2] = sm.stk[k - 1][2];
+          sm.sh[3] = 1;
+          sm.nstk = k - 1;
+        } else {
+          sm.sh[3] = 0;
+        }
+      }
+      __syncthreads();
+      if (!sm.sh[3]) break;
+      const uint32_t rs = sm.sh[0], re = sm.sh[1];
+      const uint32_t rdepth = sm.sh[2] & 0x7fffffffu;
+      const bool rfail = (sm.sh[2] >> 31) != 0;
+      uint64_t rlo = ~0ull, rhi = 0ull;
+      for (uint32_t i = rs + threadIdx.x; i < re; i += NT) {
+        const uint64_t im = sm.key[i];
+        rlo = im < rlo ? im : rlo;
+        rhi = im > rhi ? im : rhi;
+      }
+      block_minmax_u64<NT>(rlo, rhi, sm.red64);
+      if (rlo == rhi || rfail) {
+        // equal keys (ordered by position) or a failed bucket: standard sort
+        k5_bitonic<KT, CAP, NT, PAY>(sm, rs, re);
+      } else {
+        k5_level<KT, CAP, NT, PAY>(sm, rs, re, rdepth, rlo, rhi, tau);
+      }
+    }
+    // counting rank inside final segments, then the write-out.  With a
+    // payload, all reads (LDS keys and the payload, which may live in the very
+    // range being written) happen before a barrier and all writes after it.
+    // Keys alone in their segment (the common case) take their place at once;
+    // the others are ranked in a second, non-unrolled pass.
     uint32_t rr[EPT], vv[EPT];
-    uint64_t* ok = ok_ + it.off;
+    uint32_t multi = 0;  // bit kq: the key sits in a segment of several keys
 #pragma unroll
     for (int kq = 0; kq < EPT; ++kq) {
       const uint32_t i = threadIdx.x + kq * NT;
@@ -1429,22 +1577,45 @@ __global__ __launch_bounds__(NT, K5Occ<CAP>::v) void k_lds_sort(Plan p, int cls)
       if (i < m) {
         const uint32_t sg = sm.seg[i];
         const uint32_t a = sg & 0xffffu, b = sg >> 16;
-        const uint64_t k = sm.key[i];
-        const uint32_t ps = sm.pos[i];
-        uint32_t rnk = a;
         if (b - a > 1) {
-          for (uint32_t q = a; q < b; ++q) {
-            const uint64_t kq2 = sm.key[q];
-            rnk += (kq2 < k) || (kq2 == k && sm.pos[q] < ps);
-          }
-        }
-        rr[kq] = rnk;
-        if (PAY) {
-          vv[kq] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
-        } else if (rnk < m) {
-          ok[rnk] = bits_of_img<KT>(k);
+          multi |= 1u << kq;
         } else {
-          flag_internal(c);
+          rr[kq] = a;
+          if (!PAY) ok[a] = bits_of_img<KT>(sm.key[i]);
+        }
+      }
+    }
+#pragma unroll 1
+    for (uint32_t mm = multi; mm != 0; mm &= mm - 1) {
+      const int kq = __builtin_ctz(mm);
+      const uint32_t i = threadIdx.x + kq * NT;
+      const uint32_t sg = sm.seg[i];
+      const uint32_t a = sg & 0xffffu, b = sg >> 16;
+      const uint64_t k = sm.key[i];
+      const uint32_t ps = PAY ? (uint32_t)sm.pos[i] : i;
+      uint32_t rnk = a;
+      for (uint32_t q = a; q < b; ++q) {
+        const uint64_t kq2 = sm.key[q];
+        const uint32_t pq = PAY ? (uint32_t)sm.pos[q] : q;
+        rnk += (kq2 < k) || (kq2 == k && pq < ps);
+      }
+      if (PAY) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (j == kq) rr[j] = rnk;
+      } else if (rnk < m) {
+        ok[rnk] = bits_of_img<KT>(k);
+      } else {
+        flag_internal(c);
+      }
+    }
+    if (PAY) {
+#pragma unroll
+      for (int kq = 0; kq < EPT; ++kq) {
+        const uint32_t i = threadIdx.x + kq * NT;
+        if (i < m) {
+          const uint32_t ps = sm.pos[i];
+          vv[kq] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
         }
       }
     }
