@@ -15,33 +15,48 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l ? (~0ull >> (64 - l)) : 0ull;
 }
 
-// Inclusive scan of one uint32 across the 64 lanes of a wave.
+// Inclusive scan of one uint32 across the 64 lanes of a wave, with DPP lane
+// moves (no LDS crossbar): shifts by 1, 2, 4, 8 inside each row of 16 lanes,
+// then the row totals are carried by row broadcasts of lanes 15 and 31.
+// Lanes that have no source keep `old` = 0, so they add nothing.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (l >= d) x += y;
-  }
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return x;
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint64_t o = __shfl_xor(v, d, 64);
-    v = o < v ? o : v;
-  }
-  return v;
+// One step of a wave-wide min / max scan on uint64 values (two 32-bit DPP
+// moves); lanes without a source see the identity `fill`.
+template <int CTRL, int ROWMASK, bool MAX>
+__device__ __forceinline__ uint64_t dpp_minmax_step(uint64_t v) {
+  constexpr int fill = MAX ? 0 : -1;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(fill, (int)(uint32_t)v, CTRL, ROWMASK, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(fill, (int)(uint32_t)(v >> 32), CTRL, ROWMASK, 0xf, false);
+  const uint64_t o = ((uint64_t)hi << 32) | lo;
+  return MAX ? (o > v ? o : v) : (o < v ? o : v);
 }
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint64_t o = __shfl_xor(v, d, 64);
-    v = o > v ? o : v;
-  }
-  return v;
+
+// Minimum / maximum over the wave, returned to every lane: an inclusive DPP
+// scan leaves the result in lane 63, which is then read as a scalar.
+template <bool MAX>
+__device__ __forceinline__ uint64_t wave_reduce_u64(uint64_t v) {
+  v = dpp_minmax_step<0x111, 0xf, MAX>(v);
+  v = dpp_minmax_step<0x112, 0xf, MAX>(v);
+  v = dpp_minmax_step<0x114, 0xf, MAX>(v);
+  v = dpp_minmax_step<0x118, 0xf, MAX>(v);
+  v = dpp_minmax_step<0x142, 0xa, MAX>(v);
+  v = dpp_minmax_step<0x143, 0xc, MAX>(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
 }
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) { return wave_reduce_u64<false>(v); }
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) { return wave_reduce_u64<true>(v); }
 
 // Exclusive scan of one value per thread across a workgroup of NT threads.
 // `red` holds at least NT/64 + 1 words of LDS.  Returns the exclusive prefix;
