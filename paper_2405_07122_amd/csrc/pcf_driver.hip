@@ -21,11 +21,13 @@
 
 // Compile-time variants (defaults: the measured best on MI355X):
 //   PCF_KEYS_SCATTER 0: keys-only levels use the generic scatter kernel;
-//                    1: the three-barrier keys-only kernel, 4096-key tiles;
-//                    2: the same with 8192-key tiles.
+//                    1: the three-barrier keys-only kernel, 4096-key tiles
+//                       (default; about 1 % faster);
+//                    2: the same with 8192-key tiles (one workgroup per CU:
+//                       25 % slower).
 //   PCF_K5_CLASSES   2: LDS-finish classes <= 2048 and <= 8192 keys; 3: adds <= 4096.
 #ifndef PCF_KEYS_SCATTER
-#define PCF_KEYS_SCATTER 0
+#define PCF_KEYS_SCATTER 1
 #endif
 #ifndef PCF_K5_CLASSES
 #define PCF_K5_CLASSES 3

@@ -66,10 +66,11 @@ __host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nb
   return l;
 }
 
-// LDS layout of the keys-only scatter: counters double-buffered across tiles
-// so that a tile needs three barriers.
+// LDS layout of the keys-only scatter: a tile needs three barriers because
+// the write-out reads per-bucket bases (wbase) that the next tile's offset
+// update cannot touch before the next tile's first barrier.
 struct ScatterKeysLds {
-  uint32_t tab, runoff, tstart, tcnt, mmlo, mmhi, cmapf, sk, sb, total;
+  uint32_t tab, runoff, tstart, wbase, tcnt, mmlo, mmhi, cmapf, sk, sb, total;
 };
 __host__ __device__ inline ScatterKeysLds scatter_keys_lds(uint32_t max_bins, uint32_t nbmax,
                                                            int ts) {
@@ -81,9 +82,10 @@ __host__ __device__ inline ScatterKeysLds scatter_keys_lds(uint32_t max_bins, ui
     return r;
   };
   l.tab = take(2u * (max_bins + 1));
-  l.runoff = take(2u * 4u * nbmax);
-  l.tstart = take(2u * 4u * (nbmax + 1));
-  l.tcnt = take(2u * 4u * nbmax);
+  l.runoff = take(4u * nbmax);
+  l.tstart = take(4u * nbmax);
+  l.wbase = take(4u * nbmax);
+  l.tcnt = take(4u * nbmax);
   l.mmlo = take(8u * nbmax);
   l.mmhi = take(8u * nbmax);
   l.cmapf = take(1u * nbmax);

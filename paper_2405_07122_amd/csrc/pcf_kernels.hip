@@ -539,7 +539,9 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
     block_scan_array<NT, false>(st, nb, red);
     if (threadIdx.x == 0) st[nb] = nd.len;
     __syncthreads();
-    const uint32_t lds_grp = nd.kind == NK_RADIX ? BC_LDS_STD : BC_LDS_PCF;
+    // buckets of a radix node that fit LDS are finished by the in-LDS PCF
+    // levels, which are themselves a correct standard sort of them
+    const uint32_t lds_grp = BC_LDS_PCF;
     for (uint32_t q = threadIdx.x; q < nb; q += NT) {
       bs[q] = st[q];
       const uint32_t sz = st[q + 1] - st[q];
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
       if (sz == 0) {
         k = BC_EMPTY;
       } else if (nd.kind == NK_RADIX) {
-        k = sz <= cap ? BC_LDS_STD : BC_GLB_RADIX;
+        k = sz <= cap ? BC_LDS_PCF : BC_GLB_RADIX;
       } else {
         const bool fail = sz >= nd.delta;  // Algorithm 1: |c_j| >= delta
         k = sz <= cap ? (fail ? BC_LDS_STD : BC_LDS_PCF) : (fail ? BC_GLB_RADIX : BC_GLB_PCF);
@@ -989,10 +991,11 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
 
 
 // Keys only: tile ranks from LDS atomics (order inside a bucket is not
-// observable for keys alone), counters double-buffered across tiles so a tile
-// costs three barriers: rank | scan | stage | write.
+// observable for keys alone).  A tile costs three barriers:
+//   rank (LDS atomics) | wave 0: tile bucket starts, write bases, run offsets |
+//   stage in bucket order | write runs (overlaps the next tile's rank phase).
 template <int KT, int NT, int TS>
-__global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO io, uint32_t max_bins,
+__global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan p, int L, LevelIO io, uint32_t max_bins,
                                                      uint32_t nbmax) {
   constexpr int NW = NT / 64;
   constexpr int PW = TS / NW;
@@ -1001,9 +1004,10 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
   extern __shared__ __align__(16) unsigned char lds[];
   const ScatterKeysLds lay = scatter_keys_lds(max_bins, nbmax, TS);
   uint16_t* tab = reinterpret_cast<uint16_t*>(lds + lay.tab);
-  uint32_t* runoff2 = reinterpret_cast<uint32_t*>(lds + lay.runoff);  // [2][nbmax]
-  uint32_t* tstart2 = reinterpret_cast<uint32_t*>(lds + lay.tstart);  // [2][nbmax + 1]
-  uint32_t* tcnt2 = reinterpret_cast<uint32_t*>(lds + lay.tcnt);      // [2][nbmax]
+  uint32_t* runoff = reinterpret_cast<uint32_t*>(lds + lay.runoff);
+  uint32_t* tstart = reinterpret_cast<uint32_t*>(lds + lay.tstart);
+  uint32_t* wbase = reinterpret_cast<uint32_t*>(lds + lay.wbase);
+  uint32_t* tcnt = reinterpret_cast<uint32_t*>(lds + lay.tcnt);
   unsigned long long* mmlo = reinterpret_cast<unsigned long long*>(lds + lay.mmlo);
   unsigned long long* mmhi = reinterpret_cast<unsigned long long*>(lds + lay.mmhi);
   uint8_t* cmapf = reinterpret_cast<uint8_t*>(lds + lay.cmapf);
@@ -1025,6 +1029,7 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
     chunk_range(nd, un.chunk, cb, ce);
     const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
     if (nd.state == NS_DONE) {
+      // single-valued node: already in order; move it to the output if needed
       uint64_t* o = ok_ + nd.off;
       if ((const void*)o != nd.src)
         for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) o[i] = src[i];
@@ -1038,8 +1043,8 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
     const uint32_t* col = p.cm[s] + nd.cm_off;
     bool glb = false;
     for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-      runoff2[q] = bs[q] + col[(uint64_t)q * C + un.chunk];
-      tcnt2[q] = 0u;
+      runoff[q] = bs[q] + col[(uint64_t)q * C + un.chunk];
+      tcnt[q] = 0u;
       const bool g = cm[q] >= 0;
       cmapf[q] = g ? 1 : 0;
       glb |= g;
@@ -1049,20 +1054,16 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
     const bool any_glb = __syncthreads_or(glb) != 0;
     const Bucketer<KT> bk = make_bucketer<KT>(nd, tab);
 
+    // software pipeline: the next tile's keys are in flight while this one
+    // is ranked, staged and written
     uint64_t key[R], nkey[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = w * PW + r * 64 + l;
       nkey[r] = cb + i < ce ? __builtin_nontemporal_load(src + cb + i) : 0ull;
     }
-    uint32_t par = 0;
-    for (uint32_t t0 = cb; t0 < ce; t0 += TS, par ^= 1u) {
+    for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
       const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
-      uint32_t* runoff = runoff2 + par * nbmax;
-      uint32_t* runoff_n = runoff2 + (par ^ 1u) * nbmax;
-      uint32_t* tstart = tstart2 + par * (nbmax + 1);
-      uint32_t* tcnt = tcnt2 + par * nbmax;
-      uint32_t* tcnt_n = tcnt2 + (par ^ 1u) * nbmax;
 #pragma unroll
       for (int r = 0; r < R; ++r) key[r] = nkey[r];
       const uint32_t t1 = t0 + TS;
@@ -1073,26 +1074,35 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
           nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(src + t1 + i) : 0ull;
         }
       }
-      // A: bucket, rank inside the tile's bucket, child ranges
+      // A: bucket of every key (all table reads issued before any atomic),
+      // rank inside the tile's bucket, child ranges
+      uint32_t qq[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = w * PW + r * 64 + l;
+        uint32_t q = i < tn ? bk.finish(qq[r]) : 0u;
+        if (q >= nb) {  // range check: cannot happen for a consistent model
+          flag_internal(c);
+          q = nb - 1;
+        }
+        qq[r] = q;
+      }
       uint32_t code[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
         const bool valid = i < tn;
-        uint32_t q = valid ? bk(key[r]) : 0u;
-        if (q >= nb) {  // range check: cannot happen for a consistent model
-          flag_internal(c);
-          q = nb - 1;
-        }
-        const uint32_t q0 = __shfl(q, 0, 64);
+        const uint32_t q = qq[r];
+        const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
         const uint64_t act = __ballot(valid);
-        const bool uni = act == ~0ull && __all(q == q0);
         uint32_t rk = 0;
-        if (uni) {
-          // the whole wave in one bucket (runs of duplicates)
+        if (act == ~0ull && __all(q == q0)) {
+          // the whole wave in one bucket (runs of near-equal keys)
           uint32_t b0 = 0;
           if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
-          rk = __shfl(b0, 0, 64) + l;
+          rk = __builtin_amdgcn_readfirstlane(b0) + l;
           if (any_glb && cmapf[q0]) {
             const uint64_t im = img_of<KT>(key[r]);
             const uint64_t wlo = wave_min_u64(im), whi = wave_max_u64(im);
@@ -1112,20 +1122,23 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
         code[r] = (q << 16) | rk;
       }
       __syncthreads();
-      // B: bucket starts of the tile (wave 0), next tile's run offsets and counters
+      // B (wave 0): tile bucket starts, write bases, next run offsets, counters
       if (w == 0) {
         uint32_t carry = 0;
         for (uint32_t q0 = 0; q0 < nb; q0 += 64) {
           const uint32_t q = q0 + l;
           const uint32_t v = q < nb ? tcnt[q] : 0u;
           const uint32_t x = wave_incl_scan(v);
-          if (q < nb) tstart[q] = carry + x - v;
-          carry += __shfl(x, 63, 64);
+          if (q < nb) {
+            const uint32_t st = carry + x - v;
+            const uint32_t ro = runoff[q];
+            tstart[q] = st;
+            wbase[q] = ro - st;
+            runoff[q] = ro + v;
+            tcnt[q] = 0u;
+          }
+          carry += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
         }
-      }
-      for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-        runoff_n[q] = runoff[q] + tcnt[q];
-        tcnt_n[q] = 0u;
       }
       __syncthreads();
       // C: stage keys in bucket order
@@ -1145,10 +1158,12 @@ __global__ __launch_bounds__(NT, 4) void k_scatter_keys(Plan p, int L, LevelIO i
       }
       __syncthreads();
       // D: write runs (consecutive staged keys of one bucket go to consecutive
-      // addresses); the next tile's rank phase touches only the other buffers
+      // addresses); no barrier after it: the next tile's rank phase touches
+      // only tcnt and the min/max, and its bucket-start phase comes after the
+      // next barrier
       for (uint32_t i = threadIdx.x; i < tn; i += NT) {
         const uint32_t q = sb[i];
-        const uint64_t dst = nd.off + runoff[q] + (i - tstart[q]);
+        const uint64_t dst = nd.off + (uint32_t)(wbase[q] + i);
         if (dst >= nd.off + nd.len) {
           flag_internal(c);
           continue;
@@ -1555,7 +1570,11 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
         rhi = im > rhi ? im : rhi;
       }
       block_minmax_u64<NT>(rlo, rhi, sm.red64);
-      if (rlo == rhi || rfail) {
+      if (rlo == rhi && !PAY) {
+        // equal keys alone: any order is the sorted order
+        for (uint32_t i = rs + threadIdx.x; i < re; i += NT) sm.seg[i] = i | ((i + 1) << 16);
+        __syncthreads();
+      } else if (rlo == rhi || rfail) {
         // equal keys (ordered by position) or a failed bucket: standard sort
         k5_bitonic<KT, CAP, NT, PAY>(sm, rs, re);
       } else {
