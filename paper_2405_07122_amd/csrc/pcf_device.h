@@ -267,11 +267,17 @@ __device__ __host__ inline void node_params(uint32_t len, uint32_t kind, const P
   const uint32_t tgt = (len + pol.target_child - 1) / pol.target_child;
   nb = 2;
   while (nb < tgt && nb < pol.max_buckets) nb <<= 1;
+  delta = root34(len);
+  // bins and samples: bins_per_bucket / samples_per_bucket per bucket, and
+  // on large arrays at least delta / 64 (a scaled form of the paper's
+  // alpha = beta = floor(n^{3/4})), so that a dense region of a skewed
+  // distribution still spreads over several bins
   beta = pol.bins_per_bucket * nb;
+  if (delta / 64 > beta) beta = delta / 64;
   if (beta > pol.max_bins) beta = pol.max_bins;
   alpha = pol.samples_per_bucket * nb;
+  if (beta > alpha) alpha = beta;
   if (alpha > pol.max_samples) alpha = pol.max_samples;
-  delta = root34(len);
 }
 
 __device__ __host__ inline uint32_t bits_for(uint32_t nb) {

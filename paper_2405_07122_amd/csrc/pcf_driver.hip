@@ -50,7 +50,7 @@ static pcf_policy g_pol = {
     /*max_buckets*/ 256,
     /*target_child*/ 2048,
     /*bins_per_bucket*/ 16,
-    /*max_bins*/ 4096,
+    /*max_bins*/ 16383,
     /*samples_per_bucket*/ 16,
     /*max_samples*/ 65536,
     /*chunk_keys*/ 16384,
@@ -205,9 +205,13 @@ Layout make_layout(size_t n, int has_pay, uint32_t nseg, const pcf_policy& pol, 
   // than 2 ceil(len / target) + 2
   const uint64_t aux = std::max<uint64_t>(nodes * RADIX_NB,
                                           2 * n / pol.target_child + 4 * nodes + trace_nb) + 64;
-  const uint64_t table = std::min<uint64_t>(nodes * (pol.max_bins + 1) + trace_beta + 1,
-                                            nodes + (uint64_t)pol.bins_per_bucket * aux +
-                                                trace_beta + 1);
+  // bin tables of a level: a node has max(bins_per_bucket * buckets, delta / 64)
+  // bins (at most max_bins); delta / 64 exceeds 16 * 256 bins only for nodes of
+  // more than 2^24 keys
+  const uint64_t table = std::min<uint64_t>(
+      nodes * (pol.max_bins + 1) + trace_beta + 1,
+      nodes + (uint64_t)pol.bins_per_bucket * aux + (n / (1ull << 24) + 1) * (pol.max_bins + 1) +
+          trace_beta + 1);
   const uint64_t cmc = aux + nbmax * (n / std::max<uint64_t>(pol.chunk_keys, 1) + 1);
   // LDS items: every key belongs to one item; items start at window crossings
   // or big buckets (<= 2n/half), failed buckets (>= delta > cap^{3/4}), runs

@@ -51,7 +51,7 @@ __host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nb
     o += (bytes + 15u) & ~15u;
     return r;
   };
-  l.tab = take(2u * (max_bins + 1));
+  l.tab = take((nbmax <= 256 ? 1u : 2u) * (max_bins + 1));  // bucket ids as bytes when they fit
   l.wcnt = take(pay ? 2u * nw * nbmax : 0u);
   l.runoff = take(4u * nbmax);
   l.tstart = take(4u * (nbmax + 1));
@@ -81,7 +81,7 @@ __host__ __device__ inline ScatterKeysLds scatter_keys_lds(uint32_t max_bins, ui
     o += (bytes + 15u) & ~15u;
     return r;
   };
-  l.tab = take(2u * (max_bins + 1));
+  l.tab = take((nbmax <= 256 ? 1u : 2u) * (max_bins + 1));  // bucket ids as bytes when they fit
   l.runoff = take(4u * nbmax);
   l.tstart = take(4u * nbmax);
   l.wbase = take(4u * nbmax);

@@ -331,9 +331,18 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       for (uint32_t i = threadIdx.x; i <= beta; i += NT) hist[i] = 0u;
       __syncthreads();
       const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
-      for (uint32_t j = threadIdx.x; j < alpha; j += NT) {
-        const uint32_t pos = sample_pos(nd.seed, j, nd.len);
-        atomicAdd(&hist[bin_of<KT>(f, src[pos])], 1u);
+      // samples in batches of 8 per thread: all loads issued before any atomic
+      constexpr int SB = 8;
+      for (uint32_t j0 = 0; j0 < alpha; j0 += SB * NT) {
+        uint64_t v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const uint32_t j = j0 + k * NT + threadIdx.x;
+          v[k] = j < alpha ? src[sample_pos(nd.seed, j, nd.len)] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k)
+          if (j0 + k * NT + threadIdx.x < alpha) atomicAdd(&hist[bin_of<KT>(f, v[k])], 1u);
       }
       __syncthreads();
       block_scan_array<NT, true>(hist, beta + 1, red);
@@ -341,8 +350,15 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
         for (uint32_t i = threadIdx.x; i <= beta; i += NT) p.trace_b[i] = hist[i];
       const uint32_t gamma = nb - 1;
       uint16_t* tab = p.table[s] + nd.table_off;
-      for (uint32_t i = threadIdx.x; i <= beta; i += NT)
-        tab[i] = (uint16_t)(((uint64_t)hist[i] * gamma) / alpha);
+      // b_i <= alpha and gamma < 2^11: with alpha <= 2^21 the product fits
+      // 32 bits and the exact quotient takes the cheaper 32-bit division
+      if (alpha <= (1u << 21)) {
+        for (uint32_t i = threadIdx.x; i <= beta; i += NT)
+          tab[i] = (uint16_t)((hist[i] * gamma) / alpha);
+      } else {
+        for (uint32_t i = threadIdx.x; i <= beta; i += NT)
+          tab[i] = (uint16_t)(((uint64_t)hist[i] * gamma) / alpha);
+      }
     }
     if (threadIdx.x == 0) {
       nd.kind = kind;
@@ -366,13 +382,16 @@ struct Bucketer {
   uint64_t lo_img;
   uint32_t shift;
   uint32_t radix;
-  const uint16_t* tab;  // LDS copy of T
+  uint32_t narrow;      // T held as bytes (at most 256 buckets)
+  const void* tab;      // LDS copy of T
   __device__ __forceinline__ uint32_t index(uint64_t bits) const {
     if (radix) return (uint32_t)((img_of<KT>(bits) - lo_img) >> shift);
     return bin_of<KT>(f, bits);
   }
   __device__ __forceinline__ uint32_t finish(uint32_t idx) const {
-    return radix ? idx : (uint32_t)tab[idx];
+    if (radix) return idx;
+    return narrow ? (uint32_t) reinterpret_cast<const uint8_t*>(tab)[idx]
+                  : (uint32_t) reinterpret_cast<const uint16_t*>(tab)[idx];
   }
   __device__ __forceinline__ uint32_t operator()(uint64_t bits) const {
     return finish(index(bits));
@@ -380,11 +399,13 @@ struct Bucketer {
 };
 
 template <int KT>
-__device__ __forceinline__ Bucketer<KT> make_bucketer(const Node& nd, const uint16_t* tab_lds) {
+__device__ __forceinline__ Bucketer<KT> make_bucketer(const Node& nd, const void* tab_lds,
+                                                     bool narrow = false) {
   Bucketer<KT> bk;
   bk.lo_img = nd.min_img;
   bk.shift = nd.shift;
   bk.radix = nd.kind == NK_RADIX;
+  bk.narrow = narrow ? 1u : 0u;
   bk.tab = tab_lds;
   const uint64_t lob = bits_of_img<KT>(nd.min_img);
   bk.f.lo_bits = lob;
@@ -414,13 +435,16 @@ __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
   const uint32_t nu = c->lv[L].num_units;
   if (!ctl_ok(c)) return;
   const int l = lane_id();
+  uint32_t tab_node = 0xffffffffu;  // node whose table the LDS holds
   for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
     const Unit un = p.units[s][u];
     const Node& nd = p.nodes[s][un.node];
     if (nd.state != NS_ACTIVE) continue;
     const uint32_t nb = nd.nb;
-    if (nd.kind == NK_PCF)
+    if (nd.kind == NK_PCF && un.node != tab_node) {
       for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = p.table[s][nd.table_off + i];
+      tab_node = un.node;
+    }
     for (uint32_t i = threadIdx.x; i < nb; i += NT) hist[i] = 0u;
     __syncthreads();
     const Bucketer<KT> bk = make_bucketer<KT>(nd, tab);
@@ -744,7 +768,8 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
   static_assert(PW % 64 == 0, "tile must split into whole wave rounds");
   extern __shared__ __align__(16) unsigned char lds[];
   const ScatterLds lay = scatter_lds(max_bins, nbmax, NW, TS, PAY);
-  uint16_t* tab = reinterpret_cast<uint16_t*>(lds + lay.tab);
+  unsigned char* tab = lds + lay.tab;  // T as bytes when nbmax <= 256, else uint16
+  const bool tab8 = nbmax <= 256;
   uint16_t* wcnt = reinterpret_cast<uint16_t*>(lds + lay.wcnt);
   uint32_t* runoff = reinterpret_cast<uint32_t*>(lds + lay.runoff);
   uint32_t* tstart = reinterpret_cast<uint32_t*>(lds + lay.tstart);
@@ -763,6 +788,7 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
   if (!ctl_ok(c)) return;
   const int l = lane_id(), w = wave_id();
   uint64_t* dk = reinterpret_cast<uint64_t*>(io.dst_keys);
+  uint32_t tab_node = 0xffffffffu;  // node whose table the LDS holds
   uint32_t* dv = io.dst_vals;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
 
@@ -788,8 +814,15 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
       continue;
     }
     const uint32_t nb = nd.nb, nbits = nd.nbits, C = nd.nchunks;
-    if (nd.kind == NK_PCF)
-      for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = p.table[s][nd.table_off + i];
+    if (nd.kind == NK_PCF && un.node != tab_node) {
+      tab_node = un.node;
+      const uint16_t* tg = p.table[s] + nd.table_off;
+      if (tab8)
+        for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = (unsigned char)tg[i];
+      else
+        for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT)
+          reinterpret_cast<uint16_t*>(tab)[i] = tg[i];
+    }
     const uint32_t* bs = p.bstart[s] + nd.aux_off;
     const int32_t* cm = p.cmap[s] + nd.aux_off;
     const uint32_t* col = p.cm[s] + nd.cm_off;
@@ -805,7 +838,7 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
     bool glb = false;
     for (uint32_t q = threadIdx.x; q < nb; q += NT) glb |= cm[q] >= 0;
     const bool any_glb = __syncthreads_or(glb) != 0;
-    const Bucketer<KT> bk = make_bucketer<KT>(nd, tab);
+    const Bucketer<KT> bk = make_bucketer<KT>(nd, tab, tab8);
     const uint32_t* vsrc = nd.vsrc;
     const bool iota = PAY && vsrc == nullptr;
 
@@ -1003,7 +1036,8 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
   static_assert(PW % 64 == 0, "tile must split into whole wave rounds");
   extern __shared__ __align__(16) unsigned char lds[];
   const ScatterKeysLds lay = scatter_keys_lds(max_bins, nbmax, TS);
-  uint16_t* tab = reinterpret_cast<uint16_t*>(lds + lay.tab);
+  unsigned char* tab = lds + lay.tab;  // T as bytes when nbmax <= 256, else uint16
+  const bool tab8 = nbmax <= 256;
   uint32_t* runoff = reinterpret_cast<uint32_t*>(lds + lay.runoff);
   uint32_t* tstart = reinterpret_cast<uint32_t*>(lds + lay.tstart);
   uint32_t* wbase = reinterpret_cast<uint32_t*>(lds + lay.wbase);
@@ -1020,6 +1054,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
   if (!ctl_ok(c)) return;
   const int l = lane_id(), w = wave_id();
   uint64_t* dk = reinterpret_cast<uint64_t*>(io.dst_keys);
+  uint32_t tab_node = 0xffffffffu;  // node whose table the LDS holds
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
 
   for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
@@ -1036,8 +1071,15 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
       continue;
     }
     const uint32_t nb = nd.nb, C = nd.nchunks;
-    if (nd.kind == NK_PCF)
-      for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = p.table[s][nd.table_off + i];
+    if (nd.kind == NK_PCF && un.node != tab_node) {
+      tab_node = un.node;
+      const uint16_t* tg = p.table[s] + nd.table_off;
+      if (tab8)
+        for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = (unsigned char)tg[i];
+      else
+        for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT)
+          reinterpret_cast<uint16_t*>(tab)[i] = tg[i];
+    }
     const uint32_t* bs = p.bstart[s] + nd.aux_off;
     const int32_t* cm = p.cmap[s] + nd.aux_off;
     const uint32_t* col = p.cm[s] + nd.cm_off;
@@ -1052,7 +1094,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
       mmhi[q] = 0ull;
     }
     const bool any_glb = __syncthreads_or(glb) != 0;
-    const Bucketer<KT> bk = make_bucketer<KT>(nd, tab);
+    const Bucketer<KT> bk = make_bucketer<KT>(nd, tab, tab8);
 
     // software pipeline: the next tile's keys are in flight while this one
     // is ranked, staged and written
