@@ -58,17 +58,35 @@ def measured_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(x, sample: int):
-    """The CPU oracle, as it stands, on the first `sample` keys."""
+    """The CPU oracle, as it stands, on the first `sample` keys; std::sort on
+    the same keys beside it (one thread each)."""
     from oracle import oracle
     xs = x[:sample].copy()
     oracle.load()
     t0 = time.perf_counter()
     out, _, _ = oracle.sort(xs)
     dt = time.perf_counter() - t0
+    st = oracle.stdsort_seconds(xs)
     return {"value": sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample} keys of the uniform seed-1 array (fp64), "
-                      f"single thread, {dt:.2f} s"}
+                      f"single thread, {dt:.2f} s",
+            "std_sort": {"value": sample / st, "unit": "keys/s", "cores": 1,
+                         "seconds": st},
+            "host": host_cpu()}
 
 
 def batched_leg(P, reps: int, num: int):
@@ -243,6 +261,53 @@ def served_leg(P, dev: dict, rates, count: int, budget: int, streams: int):
             "rates": res}
 
 
+def stages_leg(P, n: int, reps: int = 3):
+    """Per-stage breakdown (the paper's runtime profile, App. D) for normal
+    keys and for the point-mass input of App. C (n normal keys + n copies of
+    one in-range value), keys only.  Stages: training (fit), bucketing (range,
+    count, column scan, classify, scatter), in-LDS finish; beside them the
+    share of keys (summed over levels) that the standard sort of failed
+    buckets handled (radix levels, bitonic in LDS) and that single-value
+    exits retired."""
+    import torch
+
+    from paper_2405_07122_amd import datagen
+    res = {}
+    for name, gen in (("normal", lambda: datagen.f64("normal", 2 * n, 2)),
+                      ("point_mass", lambda: datagen.adversarial("normal", n, 2))):
+        x = torch.from_numpy(gen()).to("cuda")
+        out = torch.empty_like(x)
+        ws = P.workspace(P.KEY_F64, x.numel())
+        P.pcf_sort_f64(x, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ref, _ = torch.sort(x)
+        if not torch.equal(out, ref):
+            raise RuntimeError(f"stages: {name} output differs from torch.sort")
+        P.pcf_profile_enable(True)
+        P.pcf_profile_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.pcf_sort_f64(x, out=out, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        pr = P.pcf_profile_read(reset=True)
+        P.pcf_profile_enable(False)
+        ms = {k: v["ms"] / reps for k, v in pr.items()}
+        keys = {k: v["keys"] / reps / x.numel() for k, v in pr.items()}
+        res[name] = {
+            "keys": x.numel(), "ms_per_sort": dt * 1e3,
+            "training_ms": ms["fit"],
+            "bucketing_ms": ms["range"] + ms["count"] + ms["colscan"] + ms["classify"] +
+                            ms["scatter"],
+            "lds_finish_ms": ms["lds_small"] + ms["lds_big"],
+            "setup_ms": ms["setup"],
+            "radix_key_share": keys["radix_keys"], "bitonic_key_share": keys["bitonic_keys"],
+            "single_value_key_share": keys["single_keys"]}
+        del x, out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +320,8 @@ def main():
     ap.add_argument("--argsort", action="store_true", help="also time argsort (untimed leg)")
     ap.add_argument("--no-batched", action="store_true", help="skip the segmented leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-stages", action="store_true", help="skip the per-stage profile leg")
+    ap.add_argument("--stages-n", type=int, default=10_000_000)
     ap.add_argument("--served-rates", default="200,1000,5000")
     ap.add_argument("--served-count", type=int, default=2000)
     ap.add_argument("--served-streams", type=int, default=4)
@@ -345,6 +412,9 @@ def main():
             pcfsort.pcf_argsort(dev[dists[k % len(dists)]], keys_out=out, idx_out=idx, ws=wsa)
         torch.cuda.synchronize()
         extra["argsort_keys_per_s"] = reps * n / (time.perf_counter() - ta)
+
+    if not args.no_stages:
+        extra["stages"] = stages_leg(pcfsort, args.stages_n)
 
     if not args.no_served:
         extra["served"] = served_leg(pcfsort, dev, [float(r) for r in args.served_rates.split(",")],

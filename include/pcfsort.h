@@ -159,7 +159,11 @@ typedef enum {
     PCF_K_SCATTER = 6,  /* stable scatter into contiguous buckets */
     PCF_K_LDS_SMALL = 7,/* in-LDS finish, arrays of up to 2048 keys */
     PCF_K_LDS_BIG = 8,  /* in-LDS finish, arrays of up to 8192 keys */
-    PCF_K_COUNT_KINDS = 9
+    /* key counts only (launches and ms stay 0), summed over levels: */
+    PCF_K_RADIX_KEYS = 9,   /* keys bucketed by radix levels (standard sort of failed buckets) */
+    PCF_K_BITONIC_KEYS = 10,/* keys bitonic-sorted in LDS (failed buckets and bins, equal keys) */
+    PCF_K_SINGLE_KEYS = 11, /* keys in arrays found single-valued (early exit) */
+    PCF_K_COUNT_KINDS = 12
 } pcf_kernel_kind;
 
 typedef struct {

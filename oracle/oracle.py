@@ -42,6 +42,28 @@ def build(out_path: str = LIB_PATH, extra_flags: list[str] | None = None) -> str
     return out_path
 
 
+STDSORT_PATH = os.path.join(HERE, "libstdsort.so")
+
+
+def build_stdsort(out_path: str = STDSORT_PATH) -> str:
+    """Compile the std::sort timing helper (a CPU baseline, not part of the oracle)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", out_path,
+           os.path.join(HERE, "std_sort_baseline.cpp")]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+def stdsort_seconds(x: np.ndarray) -> float:
+    """Sorts a copy of fp64 `x` with std::sort on one thread; returns the seconds."""
+    if not os.path.exists(STDSORT_PATH):
+        build_stdsort()
+    lib = ctypes.CDLL(STDSORT_PATH)
+    lib.stdsort_f64_seconds.restype = ctypes.c_double
+    lib.stdsort_f64_seconds.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    y = np.ascontiguousarray(x, dtype=np.float64).copy()
+    return float(lib.stdsort_f64_seconds(y.ctypes.data, y.size))
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("levels", ctypes.c_uint64),

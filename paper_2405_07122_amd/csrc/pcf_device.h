@@ -207,6 +207,9 @@ struct Ctl {
   uint32_t item_count[3];
   uint32_t n_radix_nodes, n_fail_items, n_done_nodes;
   unsigned long long item_keys[3];  // keys in the LDS items of each class (profiling)
+  // profiling: keys (summed over levels) handled by the standard sort of
+  // failed buckets (radix levels; bitonic in LDS) and by single-value exits
+  unsigned long long radix_keys, bitonic_keys, single_keys;
   LevelCtr lv[MAX_LEVELS];
 };
 

@@ -147,6 +147,9 @@ struct CallProf {
   int commit(const Ctl& hc, uint64_t n) {
     if (!on) return PCF_OK;
     std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof[PCF_K_RADIX_KEYS].keys += (double)hc.radix_keys;
+    g_prof[PCF_K_BITONIC_KEYS].keys += (double)hc.bitonic_keys;
+    g_prof[PCF_K_SINGLE_KEYS].keys += (double)hc.single_keys;
     for (size_t i = 0; i < used; ++i) {
       float ms = 0.f;
       PCF_HIP(hipEventElapsedTime(&ms, marks[i].a, marks[i].b));
@@ -817,8 +820,9 @@ int pcf_profile_read(pcf_kernel_stat* out, int reset) {
 }
 
 const char* pcf_kernel_name(int kind) {
-  static const char* names[PCF_K_COUNT_KINDS] = {"setup", "range", "fit", "count", "colscan",
-                                                 "classify", "scatter", "lds_small", "lds_big"};
+  static const char* names[PCF_K_COUNT_KINDS] = {
+      "setup",   "range",     "fit",        "count",        "colscan",      "classify",
+      "scatter", "lds_small", "lds_big",    "radix_keys",   "bitonic_keys", "single_keys"};
   return (kind >= 0 && kind < PCF_K_COUNT_KINDS) ? names[kind] : "unknown";
 }
 

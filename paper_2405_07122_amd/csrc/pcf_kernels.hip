@@ -313,6 +313,7 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
         nd.min_img = lo;
         nd.max_img = hi;
         nd.state = NS_DONE;
+        if (p.pol.prof) atomicAdd(&c->single_keys, (unsigned long long)nd.len);
       }
       __syncthreads();
       continue;
@@ -361,6 +362,7 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       }
     }
     if (threadIdx.x == 0) {
+      if (p.pol.prof && kind == NK_RADIX) atomicAdd(&c->radix_keys, (unsigned long long)nd.len);
       nd.kind = kind;
       nd.state = NS_ACTIVE;
       nd.shift = shift;
@@ -1431,7 +1433,7 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
   const uint32_t tau = p.pol.tau;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
   const int l = lane_id(), w = wave_id();
-  unsigned long long done_keys = 0;
+  unsigned long long done_keys = 0, bit_keys = 0, one_keys = 0;
   // static assignment of items to workgroups (a shared work counter would be
   // a same-address atomic per item); with PCF_K5_PREFETCH the next item's
   // keys are loaded into registers while this one is sorted
@@ -1511,6 +1513,7 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
       hi = sm.red64[NW + i] > hi ? sm.red64[NW + i] : hi;
     }
     uint64_t* ok = ok_ + it.off;
+    if (lo == hi) one_keys += m;
     if (lo == hi && KT == KT_U64) {
       // single-valued: input order is the answer (a u64 range cannot be bad)
 #pragma unroll
@@ -1612,6 +1615,8 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
         rhi = im > rhi ? im : rhi;
       }
       block_minmax_u64<NT>(rlo, rhi, sm.red64);
+      if (rlo == rhi) one_keys += re - rs;
+      else if (rfail) bit_keys += re - rs;
       if (rlo == rhi && !PAY) {
         // equal keys alone: any order is the sorted order
         for (uint32_t i = rs + threadIdx.x; i < re; i += NT) sm.seg[i] = i | ((i + 1) << 16);
@@ -1698,8 +1703,11 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
     }
     __syncthreads();
   }
-  if (p.pol.prof && threadIdx.x == 0 && done_keys)
+  if (p.pol.prof && threadIdx.x == 0 && done_keys) {
     atomicAdd(&c->item_keys[cls], done_keys);
+    if (bit_keys) atomicAdd(&c->bitonic_keys, bit_keys);
+    if (one_keys) atomicAdd(&c->single_keys, one_keys);
+  }
 }
 
 // ---------------------------------------------------------------------------

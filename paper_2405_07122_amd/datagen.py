@@ -102,6 +102,20 @@ def u64(kind: str, n: int, seed: int, distinct: int = 2_000_000, zipf_s: float =
     raise ValueError(f"unknown kind {kind}")
 
 
+def adversarial(dist: str, n: int, seed: int) -> np.ndarray:
+    """The point-mass input of the paper's robustness experiment (App. C): n
+    keys of `dist`, plus n copies of one value drawn uniformly inside
+    [x_min, x_max] of those keys, shuffled (2n keys in all)."""
+    x = f64(dist, n, seed)
+    rng = np.random.default_rng(seed + 0x5eed)
+    lo, hi = float(x.min()), float(x.max())
+    v = lo + rng.random() * (hi - lo)
+    v = min(max(v, lo), hi) + 0.0
+    out = np.concatenate([x, np.full(n, v, dtype=np.float64)])
+    rng.shuffle(out)
+    return out
+
+
 def config1() -> np.ndarray:
     """The plain workload: n = 1e6 fp64 keys, Uniform[0, 1), seed 0."""
     return f64("uniform", 1_000_000, 0)

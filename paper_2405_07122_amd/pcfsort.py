@@ -42,7 +42,7 @@ EXPORTS = [
 ]
 
 KERNEL_KINDS = ["setup", "range", "fit", "count", "colscan", "classify", "scatter", "lds_small",
-                "lds_big"]
+                "lds_big", "radix_keys", "bitonic_keys", "single_keys"]
 
 
 class PcfError(RuntimeError):

@@ -137,3 +137,15 @@ def test_quantization_condition_holds(oracle):
     """The fine-enough-quantization condition (App. A.4) on synthetic data."""
     _, _, st = oracle.sort(np.random.default_rng(0).standard_normal(300_000))
     assert 0.0 < st["max_quant_lhs"] <= 0.5
+
+
+def test_point_mass_input(oracle):
+    """The oracle on the point-mass input of App. C: sorted like the library
+    sort, with the point mass leaving through the single-value exit (or the
+    standard sort of a failed bucket) rather than by endless recursion."""
+    from paper_2405_07122_amd import datagen
+    x = datagen.adversarial("normal", 20_000, 5)
+    out, _, st = oracle.sort(x)
+    np.testing.assert_array_equal(out, np.sort(x))
+    assert st["single_valued"] + st["fail_sorts"] >= 1
+    assert st["max_depth"] <= 6
