@@ -25,6 +25,8 @@ DEPS = ["pcf_oracle.c", "pcf_oracle_impl.h", "pcf_oracle.h"]
 KEY_F64 = 0
 KEY_U64 = 1
 
+MODELS = {"pcf": 0, "spline": 1}
+
 OK = 0
 ERR_ARG = 1
 ERR_INVALID_KEY = 2
@@ -101,6 +103,7 @@ class LevelIO(ctypes.Structure):
         ("scale", ctypes.c_double),
         ("halves", ctypes.c_int),
         ("status", ctypes.c_int),
+        ("model", ctypes.c_int),
     ]
 
 
@@ -136,6 +139,10 @@ def load(path: str = LIB_PATH, rebuild_if_missing: bool = True):
     lib.pcfo_sort.argtypes = [ctypes.c_int, ctypes.c_void_p, _P32, ctypes.c_void_p, _P32,
                               ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                               ctypes.c_uint64, ctypes.POINTER(Stats)]
+    lib.pcfo_sort_model.restype = ctypes.c_int
+    lib.pcfo_sort_model.argtypes = [ctypes.c_int, ctypes.c_void_p, _P32, ctypes.c_void_p, _P32,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(Stats)]
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -188,8 +195,9 @@ def eta_f64(lo: float, hi: float, lib=None) -> float:
 
 
 def sort(keys: np.ndarray, vals: np.ndarray | None = None, seed: int = 0, segment: int = 0,
-         tau: int = 100, lib=None, want_vals: bool | None = None):
-    """Learned-Sort (Algorithm 1) of `keys`, carrying `vals` (uint32) stably.
+         tau: int = 100, lib=None, want_vals: bool | None = None, model: str = "pcf"):
+    """Learned-Sort (Algorithm 1) of `keys`, carrying `vals` (uint32) stably,
+    with the PCF model (Sec. 3.3) or the spline model (App. A.5).
 
     Returns (sorted_keys, sorted_vals or None, stats dict)."""
     lib = lib or load()
@@ -203,22 +211,23 @@ def sort(keys: np.ndarray, vals: np.ndarray | None = None, seed: int = 0, segmen
         want_vals = vals is not None
     vout = np.empty(n, dtype=np.uint32) if want_vals else None
     st = Stats()
-    rc = lib.pcfo_sort(kt, keys.ctypes.data, _p32(vals), out.ctypes.data, _p32(vout), n, seed,
-                       segment, tau, ctypes.byref(st))
+    rc = lib.pcfo_sort_model(kt, keys.ctypes.data, _p32(vals), out.ctypes.data, _p32(vout), n,
+                             seed, segment, tau, MODELS[model], ctypes.byref(st))
     if rc != OK:
         raise OracleError(rc)
     return out, vout, st.as_dict()
 
 
-def argsort(keys: np.ndarray, seed: int = 0, segment: int = 0, tau: int = 100, lib=None):
+def argsort(keys: np.ndarray, seed: int = 0, segment: int = 0, tau: int = 100, lib=None,
+            model: str = "pcf"):
     """Stable argsort: (sorted keys, input positions as uint32, stats)."""
     n = keys.shape[0]
     idx = np.arange(n, dtype=np.uint32)
-    return sort(keys, idx, seed=seed, segment=segment, tau=tau, lib=lib)
+    return sort(keys, idx, seed=seed, segment=segment, tau=tau, lib=lib, model=model)
 
 
 def sort_segmented(keys: np.ndarray, offsets: np.ndarray, vals: np.ndarray | None = None,
-                   seed: int = 0, tau: int = 100, lib=None):
+                   seed: int = 0, tau: int = 100, lib=None, model: str = "pcf"):
     """Every CSR segment sorted on its own, the segment index naming its nodes."""
     out = np.empty_like(keys)
     vout = np.empty(keys.shape[0], dtype=np.uint32) if vals is not None else None
@@ -227,7 +236,7 @@ def sort_segmented(keys: np.ndarray, offsets: np.ndarray, vals: np.ndarray | Non
         if b == a:
             continue
         k, v, _ = sort(keys[a:b], None if vals is None else vals[a:b], seed=seed, segment=s,
-                       tau=tau, lib=lib)
+                       tau=tau, lib=lib, model=model)
         out[a:b] = k
         if vout is not None:
             vout[a:b] = v
@@ -251,7 +260,7 @@ class Level:
 
 def level(keys: np.ndarray, alpha: int, beta: int, gamma: int, nseed: int,
           vals: np.ndarray | None = None, sample_idx: np.ndarray | None = None,
-          lib=None) -> Level:
+          lib=None, model: str = "pcf") -> Level:
     """One model-based bucketing with explicit parameters (trace for parity)."""
     lib = lib or load()
     keys = np.ascontiguousarray(keys)
@@ -274,6 +283,7 @@ def level(keys: np.ndarray, alpha: int, beta: int, gamma: int, nseed: int,
     io.part_keys = part.ctypes.data
     io.part_vals = _p32(pv)
     io.sample_pos = _p64(spos)
+    io.model = MODELS[model]
     rc = lib.pcfo_level(kt, keys.ctypes.data, _p32(vals), n, nseed, ctypes.byref(io))
     if rc != OK:
         raise OracleError(rc)

@@ -114,6 +114,8 @@ int pcfo_level(int key_type, const void *keys, const uint32_t *vals, uint64_t n,
     if (!io || !keys || n == 0 || io->alpha == 0 || io->beta == 0 || !io->b || !io->T ||
         !io->sizes || !io->part_keys)
         return PCFO_ERR_ARG;
+    if (io->model != PCFO_MODEL_PCF && io->model != PCFO_MODEL_SPLINE)
+        return PCFO_ERR_ARG;
     if (key_type == PCFO_KEY_F64)
         return level_entry_f64((const double *)keys, vals, n, node_seed, io);
     if (key_type == PCFO_KEY_U64)
@@ -125,6 +127,16 @@ int pcfo_sort(int key_type, const void *keys_in, const uint32_t *vals_in, void *
               uint32_t *vals_out, uint64_t n, uint64_t seed, uint64_t segment, uint64_t tau,
               pcfo_stats *stats)
 {
+    return pcfo_sort_model(key_type, keys_in, vals_in, keys_out, vals_out, n, seed, segment, tau,
+                           PCFO_MODEL_PCF, stats);
+}
+
+int pcfo_sort_model(int key_type, const void *keys_in, const uint32_t *vals_in, void *keys_out,
+                    uint32_t *vals_out, uint64_t n, uint64_t seed, uint64_t segment, uint64_t tau,
+                    int model, pcfo_stats *stats)
+{
+    if (model != PCFO_MODEL_PCF && model != PCFO_MODEL_SPLINE)
+        return PCFO_ERR_ARG;
     pcfo_stats local;
     pcfo_stats *st = stats ? stats : &local;
     memset(st, 0, sizeof *st);
@@ -134,9 +146,9 @@ int pcfo_sort(int key_type, const void *keys_in, const uint32_t *vals_in, void *
         return PCFO_ERR_ARG;
     if (key_type == PCFO_KEY_F64)
         return sort_entry_f64((const double *)keys_in, vals_in, (double *)keys_out, vals_out, n,
-                              seed, segment, tau, st);
+                              seed, segment, tau, model, st);
     if (key_type == PCFO_KEY_U64)
         return sort_entry_u64((const uint64_t *)keys_in, vals_in, (uint64_t *)keys_out, vals_out,
-                              n, seed, segment, tau, st);
+                              n, seed, segment, tau, model, st);
     return PCFO_ERR_ARG;
 }

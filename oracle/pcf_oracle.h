@@ -7,6 +7,9 @@
  * through seeded input arrays produced by a separate generator module.
  *
  * What it computes (Sato & Matsui, "PCF Learned Sort", TMLR 2025):
+ *   - optionally the Spline Learned Sort of App. A.5: the same training, and
+ *     inference F(x) = (b_{i-1} + frac * (b_i - b_{i-1})) / alpha with frac
+ *     the key's relative position inside its bin (b_{-1} = 0, 0-based bins);
  *   - Algorithm 1 (the Learned-Sort framework, Sec. 3.2): arrays shorter than
  *     tau go to the standard sort; otherwise a CDF model is trained, every
  *     key is appended to bucket floor(F(x) * gamma) (0-based here), buckets of
@@ -49,6 +52,11 @@
 #define PCFO_KEY_F64 0
 #define PCFO_KEY_U64 1
 
+/* CDF model of a bucketing: the PCF of Sec. 3.3, or the spline of App. A.5
+ * (same training; inference interpolates linearly inside the key's bin). */
+#define PCFO_MODEL_PCF 0
+#define PCFO_MODEL_SPLINE 1
+
 /* Counters filled by a full sort (all optional). */
 typedef struct {
     uint64_t levels;          /* model-based bucketings performed */
@@ -78,6 +86,8 @@ typedef struct {
     double scale;                /* RN(beta / RN(x_max - x_min)) (halved form if flagged) */
     int halves;                  /* 1 when x_max - x_min overflowed and halves were used */
     int status;                  /* 0 bucketed, 1 single-valued, 2 scale not finite */
+    /* input */
+    int model;                   /* PCFO_MODEL_PCF or PCFO_MODEL_SPLINE */
 } pcfo_level_io;
 
 uint64_t pcfo_splitmix64(uint64_t state, uint64_t k);
@@ -93,5 +103,10 @@ int pcfo_level(int key_type, const void *keys, const uint32_t *vals, uint64_t n,
 int pcfo_sort(int key_type, const void *keys_in, const uint32_t *vals_in, void *keys_out,
               uint32_t *vals_out, uint64_t n, uint64_t seed, uint64_t segment, uint64_t tau,
               pcfo_stats *stats);
+
+/* The same recursion with the given CDF model (PCFO_MODEL_*). */
+int pcfo_sort_model(int key_type, const void *keys_in, const uint32_t *vals_in, void *keys_out,
+                    uint32_t *vals_out, uint64_t n, uint64_t seed, uint64_t segment, uint64_t tau,
+                    int model, pcfo_stats *stats);
 
 #endif

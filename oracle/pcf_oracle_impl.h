@@ -127,7 +127,8 @@ static int FN(bin_setup)(FN(binfn) *f, KEY mn, KEY mx, uint64_t beta)
     return isfinite(f->s) ? 1 : 0;
 }
 
-static uint64_t FN(bin)(const FN(binfn) *f, KEY v)
+/* Position of v in bin units: RN(RN(v - x_min) * s), before the floor. */
+static double FN(pos)(const FN(binfn) *f, KEY v)
 {
     double off;
 #if IS_F64
@@ -138,12 +139,52 @@ static uint64_t FN(bin)(const FN(binfn) *f, KEY v)
 #else
     off = (double)(v - f->lo);
 #endif
-    double p = off * f->s;
+    return off * f->s;
+}
+
+static uint64_t FN(bin)(const FN(binfn) *f, KEY v)
+{
+    double p = FN(pos)(f, v);
     uint64_t k = (uint64_t)floor(p);
 #ifdef PCFO_PLANT_BIN_PLUS_ONE
     k += 1; /* planted mistake: the paper's 1-based bin leaks into 0-based code */
 #endif
     return k < f->beta ? k : f->beta;
+}
+
+/*
+ * Spline inference (App. A.5), 0-based: the key's bin k = min(beta, floor(p)),
+ * its relative position inside the bin frac = p - k (exact in fp64), and
+ * F(x) alpha = b_{k-1} + frac * (b_k - b_{k-1}) with b_{-1} = 0; the bucket is
+ * floor(F(x) gamma).  Each step is one IEEE round-to-nearest operation, in
+ * this order: t = frac * c, v = b_{k-1} + t, u = v * gamma, w = u / alpha.
+ * Every step is monotone and v never exceeds b_k, so buckets are
+ * non-decreasing in the key and agree with the PCF's at the bin thresholds.
+ */
+static uint64_t FN(spline_bucket)(const FN(binfn) *f, const uint64_t *b, uint64_t alpha,
+                                  uint64_t gamma, KEY v)
+{
+    double p = FN(pos)(f, v);
+    uint64_t k = (uint64_t)floor(p);
+    if (k > f->beta)
+        k = f->beta;
+    double frac = p - (double)k;
+#ifdef PCFO_PLANT_SPLINE_UPPER
+    uint64_t lo = b[k]; /* planted mistake: interpolate from the bin's upper value */
+#else
+    uint64_t lo = k ? b[k - 1] : 0;
+#endif
+    uint64_t c = b[k] - (k ? b[k - 1] : 0);
+#ifdef PCFO_PLANT_SPLINE_NOFRAC
+    double t = 0.0; /* planted mistake: the interpolation term is dropped */
+#else
+    double t = frac * (double)c;
+#endif
+    double vv = (double)lo + t;
+    double u = vv * (double)gamma;
+    double w = u / (double)alpha;
+    uint64_t q = (uint64_t)floor(w);
+    return q < gamma ? q : gamma;
 }
 
 /* Quantization condition of App. A.4 for the node interval [lo, hi]. */
@@ -176,7 +217,7 @@ typedef struct {
 static int FN(bucketize)(REC *a, uint64_t n, uint64_t node_seed, uint64_t alpha, uint64_t beta,
                          uint64_t gamma, const uint64_t *sample_idx, uint64_t *b_out,
                          uint64_t *T_out, uint64_t *sizes, uint64_t *sample_pos_out,
-                         FN(lvl_scalars) *sc, int *status)
+                         FN(lvl_scalars) *sc, int *status, int model)
 {
     uint64_t i, j;
     /* x_min and x_max of the whole current array (Sec. 3.3). */
@@ -247,8 +288,11 @@ static int FN(bucketize)(REC *a, uint64_t n, uint64_t node_seed, uint64_t alpha,
     /* Append every key, in input order, to its bucket. */
     VEC *c = (VEC *)calloc(gamma + 1, sizeof(VEC));
     int rc = c ? PCFO_OK : PCFO_ERR_NOMEM;
-    for (i = 0; i < n && rc == PCFO_OK; i++)
-        rc = FN(vec_push)(&c[T[FN(bin)(&f, a[i].k)]], a[i]);
+    for (i = 0; i < n && rc == PCFO_OK; i++) {
+        uint64_t q = model == PCFO_MODEL_SPLINE ? FN(spline_bucket)(&f, b, alpha, gamma, a[i].k)
+                                                : T[FN(bin)(&f, a[i].k)];
+        rc = FN(vec_push)(&c[q], a[i]);
+    }
 
     /* Concatenate the buckets back into a[]. */
     if (rc == PCFO_OK) {
@@ -275,6 +319,7 @@ static int FN(bucketize)(REC *a, uint64_t n, uint64_t node_seed, uint64_t alpha,
 
 typedef struct {
     uint64_t seed, segment, tau;
+    int model;
 } FN(ctx);
 
 /*
@@ -300,7 +345,7 @@ static int FN(ls)(REC *a, REC *tmp, uint64_t n, const FN(ctx) *cx, uint64_t dept
     FN(lvl_scalars) sc;
     int status;
     int rc = FN(bucketize)(a, n, pcfo_node_seed(cx->seed, cx->segment, depth, off), alpha, beta,
-                           gamma, NULL, NULL, NULL, sizes, NULL, &sc, &status);
+                           gamma, NULL, NULL, NULL, sizes, NULL, &sc, &status, cx->model);
     if (rc != PCFO_OK) {
         free(sizes);
         return rc;
@@ -371,7 +416,7 @@ static void FN(store)(const REC *a, uint64_t n, KEY *keys, uint32_t *vals)
 
 static int FN(sort_entry)(const KEY *keys_in, const uint32_t *vals_in, KEY *keys_out,
                           uint32_t *vals_out, uint64_t n, uint64_t seed, uint64_t segment,
-                          uint64_t tau, pcfo_stats *st)
+                          uint64_t tau, int model, pcfo_stats *st)
 {
     REC *a = NULL;
     int rc = FN(load)(keys_in, vals_in, n, &a);
@@ -382,7 +427,7 @@ static int FN(sort_entry)(const KEY *keys_in, const uint32_t *vals_in, KEY *keys
         free(a);
         return PCFO_ERR_NOMEM;
     }
-    FN(ctx) cx = {seed, segment, tau};
+    FN(ctx) cx = {seed, segment, tau, model};
     rc = FN(ls)(a, tmp, n, &cx, 0, 0, st);
     if (rc == PCFO_OK)
         FN(store)(a, n, keys_out, vals_out);
@@ -401,7 +446,7 @@ static int FN(level_entry)(const KEY *keys, const uint32_t *vals, uint64_t n, ui
     FN(lvl_scalars) sc;
     int status;
     rc = FN(bucketize)(a, n, node_seed, io->alpha, io->beta, io->gamma, io->sample_idx, io->b,
-                       io->T, io->sizes, io->sample_pos, &sc, &status);
+                       io->T, io->sizes, io->sample_pos, &sc, &status, io->model);
     if (rc == PCFO_OK) {
         memcpy(&io->min_bits, &sc.mn, sizeof(uint64_t));
         memcpy(&io->max_bits, &sc.mx, sizeof(uint64_t));

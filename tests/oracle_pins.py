@@ -252,5 +252,143 @@ def pin_depth(O, lib) -> list[str]:
     return fails
 
 
+# ---- Spline Learned Sort (App. A.5) -------------------------------------------
+
+def _bucket_of(lv, x):
+    """Bucket index of every (distinct) key of x, read off the partition."""
+    sizes = lv.sizes.astype(np.int64)
+    owner = np.repeat(np.arange(sizes.shape[0]), sizes)
+    where = {float(k) if x.dtype == np.float64 else int(k): int(j)
+             for k, j in zip(lv.part_keys, owner)}
+    return np.array([where[float(k) if x.dtype == np.float64 else int(k)] for k in x])
+
+
+def _grid_keys(beta, extra, rng):
+    """Keys on [0, beta] with x_min = 0 and x_max = beta, so the scale is
+    exactly 1 and a key's position in bin units is the key itself."""
+    mids = np.arange(beta, dtype=np.float64) + 0.5
+    ints = np.arange(beta + 1, dtype=np.float64)
+    more = np.unique(np.floor(rng.random(extra) * beta * 1024.0) / 1024.0 + 1.0 / 2048.0)
+    x = np.unique(np.concatenate([mids, ints, more]))
+    return rng.permutation(x)
+
+
+def pin_spline_library_sort(O, lib) -> list[str]:
+    """Spline Learned Sort sorts: numpy's order, stable payload, brute force."""
+    fails = []
+    cases = [(d, datagen.f64(d, 20_000, 300 + i)) for i, d in enumerate(datagen.F64_DISTS)]
+    cases += [(k, datagen.u64(k, 20_000, 400 + i, distinct=300))
+              for i, k in enumerate(datagen.U64_KINDS)]
+    cases.append(("dup_f64", np.round(datagen.f64("normal", 30_000, 8), 2) + 0.0))
+    for name, x in cases:
+        s, idx, _ = O.argsort(x, lib=lib, model="spline")
+        if not np.array_equal(s, np.sort(x, kind="stable")):
+            fails.append(f"spline {name}: keys differ from numpy sort")
+        if not np.array_equal(idx, _np_stable_argsort(x)):
+            fails.append(f"spline {name}: argsort differs from numpy stable argsort")
+    base = [1.0, 1.0, 2.0, 2.5, 3.0, 7.0]
+    for perm in itertools.permutations(range(len(base))):
+        x = np.array([base[q] for q in perm], dtype=np.float64)
+        s, idx, _ = O.argsort(x, tau=2, lib=lib, model="spline")
+        want = sorted(range(len(x)), key=lambda i: (x[i], i))
+        if list(idx) != want:
+            fails.append(f"spline permutation {perm}: got {list(idx)} want {want}")
+            break
+    return fails
+
+
+def pin_spline_identity(O, lib) -> list[str]:
+    """One sample per bin (b_i = i + 1): the spline is then the identity in bin
+    units, F(x) alpha = x, so every key's bucket is floor(x gamma / alpha); a
+    dropped interpolation term or the wrong end of the bin breaks it."""
+    fails = []
+    rng = np.random.default_rng(31)
+    for beta, gamma in ((64, 63), (500, 37), (1000, 1000)):
+        x = _grid_keys(beta, 3000, rng)
+        pos = {float(v): i for i, v in enumerate(x)}
+        sidx = np.array([pos[j + 0.5] for j in range(beta)] + [pos[float(beta)]], dtype=np.uint64)
+        alpha = beta + 1
+        lv = O.level(x, alpha, beta, gamma, 0, sample_idx=sidx, lib=lib, model="spline")
+        if not np.array_equal(lv.b.astype(np.int64), np.arange(1, beta + 2)):
+            fails.append(f"beta={beta}: b differs from i + 1")
+            continue
+        want = np.floor((x * float(gamma)) / float(alpha)).astype(np.int64)
+        got = _bucket_of(lv, x)
+        if not np.array_equal(got, want):
+            bad = int(np.sum(got != want))
+            fails.append(f"beta={beta} gamma={gamma}: {bad} keys off the closed form")
+    return fails
+
+
+def pin_spline_thresholds(O, lib) -> list[str]:
+    """The spline interpolates the PCF's values at the bin thresholds: a key on
+    the threshold t_k (position exactly k) takes the PCF bucket of bin k - 1,
+    and no key of bin k leaves the PCF range [T_{k-1}, T_k] (same samples)."""
+    fails = []
+    rng = np.random.default_rng(32)
+    for beta, gamma, alpha in ((256, 100, 300), (1000, 400, 700)):
+        x = _grid_keys(beta, 5000, rng)
+        ns = O.node_seed(5, 0, 0, 0, lib=lib)
+        sp = O.level(x, alpha, beta, gamma, ns, lib=lib, model="spline")
+        pc = O.level(x, alpha, beta, gamma, ns, lib=lib, model="pcf")
+        if not np.array_equal(sp.b, pc.b):
+            fails.append(f"beta={beta}: the two models trained differently")
+            continue
+        T = pc.T.astype(np.int64)
+        got = _bucket_of(sp, x)
+        k = np.minimum(np.floor(x).astype(np.int64), beta)
+        on = x == np.floor(x)
+        want_on = np.where(k == 0, 0, T[np.maximum(k - 1, 0)])
+        if not np.array_equal(got[on], want_on[on]):
+            fails.append(f"beta={beta}: threshold keys off the PCF value of the previous bin")
+        lo = np.where(k == 0, 0, T[np.maximum(k - 1, 0)])
+        if np.any(got < lo) or np.any(got > T[k]):
+            fails.append(f"beta={beta}: a key left its bin's PCF range")
+    return fails
+
+
+def pin_spline_level_invariants(O, lib) -> list[str]:
+    fails = []
+    rng = np.random.default_rng(33)
+    for name, x, (a, be, g) in [
+        ("uniform", datagen.f64("uniform", 20_000, 13), (500, 800, 120)),
+        ("lognormal", datagen.f64("lognormal", 20_000, 14), (1000, 300, 63)),
+        ("dups", np.round(rng.standard_normal(20_000), 1) + 0.0, (700, 700, 700)),
+        ("bursty", datagen.u64("bursty", 20_000, 16), (2000, 2000, 100)),
+    ]:
+        idx = np.arange(x.shape[0], dtype=np.uint32)
+        lv = O.level(x, a, be, g, O.node_seed(3, 0, 0, 0, lib=lib), vals=idx, lib=lib,
+                     model="spline")
+        if lv.status != 0:
+            fails.append(f"spline {name}: unexpected status {lv.status}")
+            continue
+        fails += [f"spline {m}" for m in _check_level(name, x, lv, a, be, g)]
+    return fails
+
+
+def pin_spline_lfail_depth(O, lib) -> list[str]:
+    """The spline keeps the PCF's guarantees (App. A.5): no bucket above delta
+    on uniform keys with the paper's parameters, and the depth bound."""
+    fails = []
+    n = 100_000
+    x = datagen.f64("uniform", n, 22)
+    r = O.root34(n, lib=lib)
+    for rep in range(6):
+        lv = O.level(x, r, r, r, O.node_seed(3000 + rep, 0, 0, 0, lib=lib), lib=lib,
+                     model="spline")
+        if lv.sizes.max() > r:
+            fails.append(f"spline: bucketing failure on uniform keys (rep {rep})")
+    for name, y in [("lognormal 2e5", datagen.f64("lognormal", 200_000, 10)),
+                    ("geometric 1000", np.array([2.0 ** (-i) for i in range(1000)]))]:
+        s, _, st = O.sort(y, lib=lib, model="spline")
+        if st["max_depth"] > depth_bound(y.shape[0], 100):
+            fails.append(f"spline {name}: depth {st['max_depth']} over the bound")
+        if not np.array_equal(s, np.sort(y)):
+            fails.append(f"spline {name}: not sorted")
+    return fails
+
+
 ALL_PINS = [pin_library_sort, pin_brute_force, pin_selection_sort, pin_level_invariants,
-            pin_identity_closed_form, pin_scaled_closed_form, pin_lfail, pin_depth]
+            pin_identity_closed_form, pin_scaled_closed_form, pin_lfail, pin_depth,
+            pin_spline_library_sort, pin_spline_identity, pin_spline_thresholds,
+            pin_spline_level_invariants, pin_spline_lfail_depth]

@@ -17,6 +17,8 @@ PLANTS = [
     "PCFO_PLANT_T_CEIL",
     "PCFO_PLANT_NO_FALLBACK",
     "PCFO_PLANT_SAMPLE_PREFIX",
+    "PCFO_PLANT_SPLINE_UPPER",
+    "PCFO_PLANT_SPLINE_NOFRAC",
 ]
 
 
