@@ -321,6 +321,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the segmented leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage profile leg")
+    ap.add_argument("--no-spline", action="store_true", help="skip the spline-model leg")
     ap.add_argument("--stages-n", type=int, default=10_000_000)
     ap.add_argument("--served-rates", default="200,1000,5000")
     ap.add_argument("--served-count", type=int, default=2000)
@@ -401,6 +402,25 @@ def main():
                for k, v in prof.items()}
 
     extra = {}
+    if not args.no_spline:
+        # Spline Learned Sort (App. A.5): the same workload with the spline model
+        base = pcfsort.get_policy()
+        pcfsort.set_policy(model=1)
+        wsp = pcfsort.workspace(pcfsort.KEY_F64, n)
+        pcfsort.pcf_sort_f64(chk, out=out, ws=wsp)
+        torch.cuda.synchronize()
+        if not torch.equal(out, ref):
+            log("spline: sorted output differs from torch.sort")
+            sys.exit(1)
+        reps = len(dists)
+        ts = time.perf_counter()
+        for k in range(reps):
+            pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=wsp)
+        torch.cuda.synchronize()
+        extra["spline"] = {"keys_per_s": reps * n / (time.perf_counter() - ts), "sorts": reps,
+                           "model": "spline (App. A.5) on the global levels"}
+        pcfsort.set_policy(**base)
+        del wsp
     if args.argsort:
         idx = torch.empty(n, dtype=torch.int32, device="cuda")
         wsa = pcfsort.workspace(pcfsort.KEY_F64, n, with_payload=True)

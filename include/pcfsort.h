@@ -135,7 +135,10 @@ int pcf_graph_clear(void);
  * receive beta + 1 uint64 values (prefix counts b_i and the bucket of each
  * bin), h_sizes receives gamma + 1 bucket sizes, h_scalars receives
  * {min bits, max bits, scale bits, halves, status} as 5 uint64.
- * Synchronizes `stream`.  Limits: beta <= 16383, gamma <= 2047.
+ * Synchronizes `stream`.  Limits: beta <= 16383, gamma <= 2047 (and alpha <=
+ * 65535 with the spline model).  The level uses the current policy's model;
+ * with the spline model h_T receives the prefix counts b_i the model
+ * interpolates between.
  */
 int pcf_level_trace(int key_type, const void *d_keys_in, const uint32_t *d_vals_in, size_t n,
                     uint64_t node_seed, uint32_t alpha, uint32_t beta, uint32_t gamma,
@@ -200,6 +203,9 @@ typedef struct {
     uint32_t lds_cap;            /* largest array finished in LDS, <= 8192 */
     uint32_t tau;                /* small-array threshold inside LDS (paper: 100) */
     uint32_t seed;               /* sampling seed */
+    uint32_t model;              /* CDF model of the global levels: 0 PCF (Sec. 3.3),
+                                    1 spline (Spline Learned Sort, App. A.5); the
+                                    in-LDS finish uses the PCF at one bin per key */
 } pcf_policy;
 
 /* Current process-wide policy (defaults, or what pcf_set_policy / tuning set). */

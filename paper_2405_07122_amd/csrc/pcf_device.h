@@ -106,8 +106,9 @@ struct BinFn {
   uint32_t halves;
 };
 
+// Position of a key in bin units, RN(RN(x - x_min) * s), before the floor.
 template <int KT>
-__device__ __forceinline__ uint32_t bin_of(const BinFn& f, uint64_t bits) {
+__device__ __forceinline__ double pos_of(const BinFn& f, uint64_t bits) {
   double off;
   if (KT == KT_F64) {
     const double v = __longlong_as_double((long long)bits);
@@ -115,7 +116,12 @@ __device__ __forceinline__ uint32_t bin_of(const BinFn& f, uint64_t bits) {
   } else {
     off = (double)(bits - f.lo_bits);
   }
-  const double p = off * f.s;
+  return off * f.s;
+}
+
+template <int KT>
+__device__ __forceinline__ uint32_t bin_of(const BinFn& f, uint64_t bits) {
+  const double p = pos_of<KT>(f, bits);
   const uint32_t k = (uint32_t)floor(p);
   return k < f.beta ? k : f.beta;
 }
@@ -150,7 +156,9 @@ __device__ __forceinline__ bool bin_setup(BinFn& f, uint64_t lo_img, uint64_t hi
 }
 
 // ---- work records ---------------------------------------------------------
-enum : uint32_t { NK_PCF = 0, NK_RADIX = 1 };
+// node kinds: PCF model (Sec. 3.3), radix digits (standard sort of a failed
+// bucket), spline model (App. A.5: the PCF's training, interpolated inference)
+enum : uint32_t { NK_PCF = 0, NK_RADIX = 1, NK_SPLINE = 2 };
 enum : uint32_t { NS_ACTIVE = 0, NS_DONE = 1 };
 enum : uint32_t { IF_STD = 1, IF_ROOT = 2, IF_IOTA = 4 };
 
@@ -219,6 +227,7 @@ struct PolicyDev {
   uint32_t max_buckets, target_child, bins_per_bucket, max_bins;
   uint32_t samples_per_bucket, max_samples, chunk_keys, lds_cap;
   uint32_t tau, small_cap, prof, mid_cap;
+  uint32_t model;  // 0: PCF, 1: spline (kind of every model node)
 };
 
 // LDS-finish class of an array of `len` keys (0: <= small_cap, 1: <= mid_cap, 2: larger).
@@ -281,6 +290,8 @@ __device__ __host__ inline void node_params(uint32_t len, uint32_t kind, const P
   alpha = pol.samples_per_bucket * nb;
   if (beta > alpha) alpha = beta;
   if (alpha > pol.max_samples) alpha = pol.max_samples;
+  // spline nodes keep the prefix counts b_i themselves in the 16-bit table
+  if (kind == NK_SPLINE && alpha > 65535u) alpha = 65535u;
 }
 
 __device__ __host__ inline uint32_t bits_for(uint32_t nb) {

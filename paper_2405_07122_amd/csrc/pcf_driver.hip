@@ -57,6 +57,7 @@ static pcf_policy g_pol = {
     /*lds_cap*/ 8192,
     /*tau*/ 100,
     /*seed*/ 0x5eed,
+    /*model*/ 0,
 };
 
 pcf_policy current_policy() {
@@ -90,6 +91,7 @@ int check_policy(const pcf_policy& p) {
     return PCF_ERR_INVALID_ARGUMENT;
   if (p.chunk_keys < 1024 || p.lds_cap < 2048 || p.lds_cap > 8192) return PCF_ERR_INVALID_ARGUMENT;
   if (p.tau < 16 || p.tau > 1024) return PCF_ERR_INVALID_ARGUMENT;
+  if (p.model > 1) return PCF_ERR_INVALID_ARGUMENT;
   return PCF_OK;
 }
 
@@ -331,18 +333,18 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   uint32_t sc_lds;
   if (PAY) {
     sc_ts = SC_TS_PAY;
-    sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY).total;
+    sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY, (int)pol.model).total;
     if (sc_lds > 160 * 1024 - 1024) {  // many buckets: halve the tile
       sc_ts /= 2;
-      sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY).total;
+      sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY, (int)pol.model).total;
     }
   } else {
     sc_ts = (big_keys_tile || PCF_KEYS_SCATTER == 2) ? 8192 : 4096;
-    sc_lds = PCF_KEYS_SCATTER == 0 ? scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, 4096, 0).total
-                                   : scatter_keys_lds(bins_lds, lay.nbmax, sc_ts).total;
+    sc_lds = PCF_KEYS_SCATTER == 0 ? scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, 4096, 0, (int)pol.model).total
+                                   : scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
     if (sc_lds > 160 * 1024 - 1024) {
       sc_ts = 4096;
-      sc_lds = scatter_keys_lds(bins_lds, lay.nbmax, sc_ts).total;
+      sc_lds = scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
     }
   }
   if (sc_lds > 160 * 1024 - 1024) return PCF_ERR_INVALID_ARGUMENT;
@@ -362,6 +364,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
       (uint32_t)std::max<uint64_t>(pol.chunk_keys, (a.n + 8ull * g_sc - 1) / (8ull * g_sc));
   pd.lds_cap = pol.lds_cap;
   pd.tau = pol.tau;
+  pd.model = pol.model;
   pd.small_cap = K5_SMALL_CAP;
   pd.mid_cap = PCF_K5_CLASSES == 2 ? K5_SMALL_CAP : K5_MID_CAP;
   {
@@ -484,7 +487,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
       a.h_scalars[3] = nd.halves;
       a.h_scalars[4] = nd.state == NS_DONE ? 1 : (nd.kind == NK_RADIX ? 2 : 0);
     }
-    if (nd.state == NS_ACTIVE && nd.kind == NK_PCF) {
+    if (nd.state == NS_ACTIVE && nd.kind != NK_RADIX) {
       std::vector<uint32_t> hb(beta + 1), st32(nb);
       std::vector<uint16_t> ht(beta + 1);
       PCF_HIP(hipMemcpy(hb.data(), p.trace_b, 4ull * (beta + 1), hipMemcpyDeviceToHost));
@@ -928,6 +931,7 @@ int pcf_level_trace(int key_type, const void* d_keys_in, const uint32_t* d_vals_
   if (alpha == 0 || beta == 0 || beta > MAX_BINS || gamma + 1 > MAX_NB || alpha > (1u << 24))
     return PCF_ERR_INVALID_ARGUMENT;
   if ((d_vals_in == nullptr) != (d_part_vals == nullptr)) return PCF_ERR_INVALID_ARGUMENT;
+  if (current_policy().model != 0 && alpha > 65535u) return PCF_ERR_INVALID_ARGUMENT;
   SortArgs a = {};
   a.key_type = key_type;
   a.keys_in = d_keys_in;

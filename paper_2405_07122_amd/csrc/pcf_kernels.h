@@ -43,7 +43,7 @@ struct ScatterLds {
   uint32_t tab, wcnt, runoff, tstart, tcnt, mmlo, mmhi, cmapf, sk, sv, sb, total;
 };
 __host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nbmax, int nw,
-                                                  int ts, int pay) {
+                                                  int ts, int pay, int wide_tab = 0) {
   ScatterLds l;
   uint32_t o = 0;
   auto take = [&](uint32_t bytes) {
@@ -51,7 +51,8 @@ __host__ __device__ inline ScatterLds scatter_lds(uint32_t max_bins, uint32_t nb
     o += (bytes + 15u) & ~15u;
     return r;
   };
-  l.tab = take((nbmax <= 256 ? 1u : 2u) * (max_bins + 1));  // bucket ids as bytes when they fit
+  // bucket ids as bytes when they fit; spline tables hold 16-bit prefix counts
+  l.tab = take((nbmax <= 256 && !wide_tab ? 1u : 2u) * (max_bins + 1));
   l.wcnt = take(pay ? 2u * nw * nbmax : 0u);
   l.runoff = take(4u * nbmax);
   l.tstart = take(4u * (nbmax + 1));
@@ -73,7 +74,7 @@ struct ScatterKeysLds {
   uint32_t tab, runoff, tstart, wbase, tcnt, mmlo, mmhi, cmapf, sk, sb, total;
 };
 __host__ __device__ inline ScatterKeysLds scatter_keys_lds(uint32_t max_bins, uint32_t nbmax,
-                                                           int ts) {
+                                                           int ts, int wide_tab = 0) {
   ScatterKeysLds l;
   uint32_t o = 0;
   auto take = [&](uint32_t bytes) {
@@ -81,7 +82,8 @@ __host__ __device__ inline ScatterKeysLds scatter_keys_lds(uint32_t max_bins, ui
     o += (bytes + 15u) & ~15u;
     return r;
   };
-  l.tab = take((nbmax <= 256 ? 1u : 2u) * (max_bins + 1));  // bucket ids as bytes when they fit
+  // bucket ids as bytes when they fit; spline tables hold 16-bit prefix counts
+  l.tab = take((nbmax <= 256 && !wide_tab ? 1u : 2u) * (max_bins + 1));
   l.runoff = take(4u * nbmax);
   l.tstart = take(4u * nbmax);
   l.wbase = take(4u * nbmax);

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
         alpha = a.fixed_alpha;
         delta = len + 1;
       } else {
-        node_params(len, NK_PCF, p.pol, nb, beta, alpha, delta);
+        node_params(len, p.pol.model ? NK_SPLINE : NK_PCF, p.pol, nb, beta, alpha, delta);
       }
       nch = (len + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
     }
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
         nd.len = len;
         nd.seg = s;
         nd.depth = 0;
-        nd.kind = NK_PCF;
+        nd.kind = p.pol.model ? NK_SPLINE : NK_PCF;
         nd.nchunks = nch;
         nd.unit_base = (uint32_t)ub;
         nd.aux_off = (uint32_t)ab;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
     uint32_t kind = nd.kind, shift = 0;
     const uint32_t nb = nd.nb, beta = nd.beta, alpha = nd.alpha;
     BinFn f = {};
-    if (kind == NK_PCF && !bin_setup<KT>(f, lo, hi, beta)) kind = NK_RADIX;  // scale not finite
+    if (kind != NK_RADIX && !bin_setup<KT>(f, lo, hi, beta)) kind = NK_RADIX;  // scale not finite
     if (kind == NK_RADIX) {
       // standard sort by most-significant digits of the range: nb buckets
       const uint64_t range = hi - lo;
@@ -351,9 +351,12 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
         for (uint32_t i = threadIdx.x; i <= beta; i += NT) p.trace_b[i] = hist[i];
       const uint32_t gamma = nb - 1;
       uint16_t* tab = p.table[s] + nd.table_off;
-      // b_i <= alpha and gamma < 2^11: with alpha <= 2^21 the product fits
-      // 32 bits and the exact quotient takes the cheaper 32-bit division
-      if (alpha <= (1u << 21)) {
+      if (kind == NK_SPLINE) {
+        // the spline interpolates between prefix counts: keep b_i itself
+        for (uint32_t i = threadIdx.x; i <= beta; i += NT) tab[i] = (uint16_t)hist[i];
+      } else if (alpha <= (1u << 21)) {
+        // b_i <= alpha and gamma < 2^11: the product fits 32 bits and the
+        // exact quotient takes the cheaper 32-bit division
         for (uint32_t i = threadIdx.x; i <= beta; i += NT)
           tab[i] = (uint16_t)((hist[i] * gamma) / alpha);
       } else {
@@ -385,7 +388,9 @@ struct Bucketer {
   uint32_t shift;
   uint32_t radix;
   uint32_t narrow;      // T held as bytes (at most 256 buckets)
-  const void* tab;      // LDS copy of T
+  uint32_t spline;      // the table holds prefix counts b_i (App. A.5)
+  double alpha, gamma;  // spline: sample count and last bucket index
+  const void* tab;      // LDS copy of T (or of b for the spline)
   __device__ __forceinline__ uint32_t index(uint64_t bits) const {
     if (radix) return (uint32_t)((img_of<KT>(bits) - lo_img) >> shift);
     return bin_of<KT>(f, bits);
@@ -395,8 +400,32 @@ struct Bucketer {
     return narrow ? (uint32_t) reinterpret_cast<const uint8_t*>(tab)[idx]
                   : (uint32_t) reinterpret_cast<const uint16_t*>(tab)[idx];
   }
+  // Spline bucket (App. A.5), 0-based: bin k, frac = p - k, and
+  // floor((b_{k-1} + frac (b_k - b_{k-1})) gamma / alpha), one IEEE
+  // round-to-nearest step per operation in the order t = frac * c,
+  // v = b_{k-1} + t, u = v * gamma, w = u / alpha.
+  __device__ __forceinline__ uint32_t spline_bucket(uint64_t bits) const {
+    const uint16_t* b = reinterpret_cast<const uint16_t*>(tab);
+    const double p = pos_of<KT>(f, bits);
+    uint32_t k = (uint32_t)floor(p);
+    k = k < f.beta ? k : f.beta;
+    const double frac = p - (double)k;
+    const uint32_t lo = k ? (uint32_t)b[k - 1] : 0u;
+    const uint32_t cnt = (uint32_t)b[k] - lo;
+    const double t = frac * (double)cnt;
+    const double v = (double)lo + t;
+    const double u = v * gamma;
+    const double w = u / alpha;
+    const uint32_t q = (uint32_t)floor(w);
+    const uint32_t g = (uint32_t)gamma;
+    return q < g ? q : g;
+  }
+  // bucket of a key whose index() was `idx`
+  __device__ __forceinline__ uint32_t finish2(uint32_t idx, uint64_t bits) const {
+    return spline ? spline_bucket(bits) : finish(idx);
+  }
   __device__ __forceinline__ uint32_t operator()(uint64_t bits) const {
-    return finish(index(bits));
+    return spline ? spline_bucket(bits) : finish(index(bits));
   }
 };
 
@@ -407,7 +436,10 @@ __device__ __forceinline__ Bucketer<KT> make_bucketer(const Node& nd, const void
   bk.lo_img = nd.min_img;
   bk.shift = nd.shift;
   bk.radix = nd.kind == NK_RADIX;
-  bk.narrow = narrow ? 1u : 0u;
+  bk.spline = nd.kind == NK_SPLINE;
+  bk.narrow = (narrow && !bk.spline) ? 1u : 0u;
+  bk.alpha = (double)nd.alpha;
+  bk.gamma = (double)(nd.nb - 1);
   bk.tab = tab_lds;
   const uint64_t lob = bits_of_img<KT>(nd.min_img);
   bk.f.lo_bits = lob;
@@ -443,7 +475,7 @@ __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
     const Node& nd = p.nodes[s][un.node];
     if (nd.state != NS_ACTIVE) continue;
     const uint32_t nb = nd.nb;
-    if (nd.kind == NK_PCF && un.node != tab_node) {
+    if (nd.kind != NK_RADIX && un.node != tab_node) {
       for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = p.table[s][nd.table_off + i];
       tab_node = un.node;
     }
@@ -477,7 +509,7 @@ __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
 #pragma unroll
       for (int k = 0; k < U; ++k) q[k] = bk.index(v[k]);
 #pragma unroll
-      for (int k = 0; k < U; ++k) q[k] = bk.finish(q[k]);
+      for (int k = 0; k < U; ++k) q[k] = bk.finish2(q[k], v[k]);
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const uint32_t i = base + k * NT + threadIdx.x;
@@ -636,7 +668,7 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
         }
         if (kq >= BC_GLB_PCF && has_next) {
           const uint32_t sz = st[q + 1] - st[q];
-          node_params(sz, kq == BC_GLB_RADIX ? NK_RADIX : NK_PCF, p.pol, cnb[k], cbeta[k],
+          node_params(sz, kq == BC_GLB_RADIX ? NK_RADIX : (p.pol.model ? NK_SPLINE : NK_PCF), p.pol, cnb[k], cbeta[k],
                       calpha[k], cdelta[k]);
           cnch[k] = (sz + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
           ++n_node;
@@ -730,7 +762,7 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
         ch.len = sz;
         ch.seg = nd.seg;
         ch.depth = nd.depth + 1;
-        ch.kind = radix ? NK_RADIX : NK_PCF;
+        ch.kind = radix ? NK_RADIX : (p.pol.model ? NK_SPLINE : NK_PCF);
         ch.nchunks = cnch[k];
         ch.unit_base = (uint32_t)ub;
         ch.aux_off = (uint32_t)ab;
@@ -769,9 +801,9 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
   constexpr int R = PW / 64;    // rounds per wave
   static_assert(PW % 64 == 0, "tile must split into whole wave rounds");
   extern __shared__ __align__(16) unsigned char lds[];
-  const ScatterLds lay = scatter_lds(max_bins, nbmax, NW, TS, PAY);
+  const ScatterLds lay = scatter_lds(max_bins, nbmax, NW, TS, PAY, (int)p.pol.model);
   unsigned char* tab = lds + lay.tab;  // T as bytes when nbmax <= 256, else uint16
-  const bool tab8 = nbmax <= 256;
+  const bool tab8 = nbmax <= 256 && !p.pol.model;  // spline tables hold b_i: 16 bits
   uint16_t* wcnt = reinterpret_cast<uint16_t*>(lds + lay.wcnt);
   uint32_t* runoff = reinterpret_cast<uint32_t*>(lds + lay.runoff);
   uint32_t* tstart = reinterpret_cast<uint32_t*>(lds + lay.tstart);
@@ -816,7 +848,7 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
       continue;
     }
     const uint32_t nb = nd.nb, nbits = nd.nbits, C = nd.nchunks;
-    if (nd.kind == NK_PCF && un.node != tab_node) {
+    if (nd.kind != NK_RADIX && un.node != tab_node) {
       tab_node = un.node;
       const uint16_t* tg = p.table[s] + nd.table_off;
       if (tab8)
@@ -882,7 +914,7 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
-        uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish(qq[r]) : bk(key[r])) : 0u;
+        uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish2(qq[r], key[r]) : bk(key[r])) : 0u;
         if (q >= nb) {  // range check: cannot happen for a consistent model
           flag_internal(c);
           q = nb - 1;
@@ -1037,9 +1069,9 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
   constexpr int R = PW / 64;
   static_assert(PW % 64 == 0, "tile must split into whole wave rounds");
   extern __shared__ __align__(16) unsigned char lds[];
-  const ScatterKeysLds lay = scatter_keys_lds(max_bins, nbmax, TS);
+  const ScatterKeysLds lay = scatter_keys_lds(max_bins, nbmax, TS, (int)p.pol.model);
   unsigned char* tab = lds + lay.tab;  // T as bytes when nbmax <= 256, else uint16
-  const bool tab8 = nbmax <= 256;
+  const bool tab8 = nbmax <= 256 && !p.pol.model;  // spline tables hold b_i: 16 bits
   uint32_t* runoff = reinterpret_cast<uint32_t*>(lds + lay.runoff);
   uint32_t* tstart = reinterpret_cast<uint32_t*>(lds + lay.tstart);
   uint32_t* wbase = reinterpret_cast<uint32_t*>(lds + lay.wbase);
@@ -1073,7 +1105,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
       continue;
     }
     const uint32_t nb = nd.nb, C = nd.nchunks;
-    if (nd.kind == NK_PCF && un.node != tab_node) {
+    if (nd.kind != NK_RADIX && un.node != tab_node) {
       tab_node = un.node;
       const uint16_t* tg = p.table[s] + nd.table_off;
       if (tab8)
@@ -1126,7 +1158,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
-        uint32_t q = i < tn ? bk.finish(qq[r]) : 0u;
+        uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
         if (q >= nb) {  // range check: cannot happen for a consistent model
           flag_internal(c);
           q = nb - 1;

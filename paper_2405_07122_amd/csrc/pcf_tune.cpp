@@ -254,14 +254,16 @@ struct JParser {
   }
 };
 
-const char* kFields[] = {"max_buckets", "target_child", "bins_per_bucket", "max_bins",
-                         "samples_per_bucket", "max_samples", "chunk_keys", "lds_cap", "tau",
-                         "seed"};
+constexpr int kNumFields = 11;
+const char* kFields[kNumFields] = {"max_buckets", "target_child", "bins_per_bucket", "max_bins",
+                                   "samples_per_bucket", "max_samples", "chunk_keys", "lds_cap",
+                                   "tau", "seed", "model"};
 
 uint32_t* field(pcf_policy& p, int i) {
-  uint32_t* f[] = {&p.max_buckets, &p.target_child,       &p.bins_per_bucket, &p.max_bins,
-                   &p.samples_per_bucket, &p.max_samples, &p.chunk_keys,      &p.lds_cap,
-                   &p.tau,                &p.seed};
+  uint32_t* f[kNumFields] = {&p.max_buckets, &p.target_child,       &p.bins_per_bucket,
+                             &p.max_bins,    &p.samples_per_bucket, &p.max_samples,
+                             &p.chunk_keys,  &p.lds_cap,            &p.tau,
+                             &p.seed,        &p.model};
   return f[i];
 }
 
@@ -378,7 +380,7 @@ int pcf_autotune(int key_type, int with_payload, const char* out_json) {
                  e.key_type, e.with_payload, (unsigned long long)e.min_n,
                  (unsigned long long)e.max_n, (unsigned long long)kClasses[i].rep_n, e.ms);
     pcf_policy p = e.pol;
-    for (int k = 0; k < 10; ++k)
+    for (int k = 0; k < kNumFields; ++k)
       std::fprintf(f, "%s\"%s\": %u", k ? ", " : "", kFields[k], *field(p, k));
     std::fprintf(f, "}}%s\n", i + 1 < table.size() ? "," : "");
   }
@@ -423,7 +425,7 @@ int pcf_load_tuning(const char* json_path) {
     const JVal* pol = e.get("policy");
     if (!pol || pol->kind != JVal::OBJ) return PCF_ERR_INVALID_ARGUMENT;
     te.pol = pcf::current_policy();  // fields the file omits keep the defaults
-    for (int k = 0; k < 10; ++k) {
+    for (int k = 0; k < kNumFields; ++k) {
       const JVal* v = pol->get(kFields[k]);
       if (!v) continue;
       uint64_t x;
