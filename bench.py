@@ -308,6 +308,64 @@ def stages_leg(P, n: int, reps: int = 3):
     return res
 
 
+def lfail_leg(P, n: int = 1_000_000, reps: int = 100):
+    """The bucketing-failure experiment of Sec. 4.2 (Fig. 3): alpha, beta,
+    gamma, delta = floor(n^{a,b,c,d}); six heatmaps over two of the exponents
+    in {0.05, ..., 0.95} with the other two at 0.75; `reps` uniform arrays of n
+    keys; the empirical frequency of a bucket above delta per cell, beside the
+    lemma's bound (sigma2 / sigma1 = 1).  Reports every grid and, per heatmap,
+    the cells where the bound is at most 0.5 yet failures exceed half."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2405_07122_amd import datagen
+
+    def bound(al, be, ga, de):
+        K = ga * de / (2.0 * n) - 2.0 * ga / be
+        if K < 1.0:
+            return None
+        return (2.0 * n / de) * math.exp(-(al * K / (2.0 * ga)) * (1.0 - 1.0 / K) ** 2)
+
+    grid = [round(0.05 * k, 2) for k in range(1, 20)]
+    names = "abcd"
+    pairs = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    arrays = torch.from_numpy(np.stack([datagen.f64("uniform", n, 1000 + r)
+                                        for r in range(reps)])).to("cuda")
+    cells, where = [], []
+    for hi, (i, j) in enumerate(pairs):
+        for vi in grid:
+            for vj in grid:
+                e = [0.75] * 4
+                e[i], e[j] = vi, vj
+                cells.append(tuple(max(1, int(math.floor(n ** v))) for v in e))
+                where.append((hi, vi, vj))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fails = P.pcf_lfail_grid(arrays, cells, seed=2024)
+    dt = time.perf_counter() - t0
+    maps = []
+    for hi, (i, j) in enumerate(pairs):
+        freq = [[0.0] * len(grid) for _ in grid]
+        viol, small = 0, 0
+        for c, (h, vi, vj) in enumerate(where):
+            if h != hi:
+                continue
+            f = int(fails[c]) / reps
+            freq[grid.index(vj)][grid.index(vi)] = f
+            b = bound(*cells[c])
+            if b is not None and b <= 0.5:
+                small += 1
+                viol += f > 0.5
+        maps.append({"x": names[i], "y": names[j], "fixed": 0.75, "freq_rows_y_cols_x": freq,
+                     "cells_bound_le_half": small, "of_which_failing_more_than_half": viol})
+    del arrays
+    torch.cuda.empty_cache()
+    return {"n": n, "reps": reps, "grid": grid, "runs": len(cells) * reps, "seconds": dt,
+            "heatmaps": maps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +380,8 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage profile leg")
     ap.add_argument("--no-spline", action="store_true", help="skip the spline-model leg")
+    ap.add_argument("--lfail", action="store_true",
+                    help="also run the bucketing-failure experiment (Fig. 3 protocol)")
     ap.add_argument("--stages-n", type=int, default=10_000_000)
     ap.add_argument("--served-rates", default="200,1000,5000")
     ap.add_argument("--served-count", type=int, default=2000)
@@ -432,6 +492,10 @@ def main():
             pcfsort.pcf_argsort(dev[dists[k % len(dists)]], keys_out=out, idx_out=idx, ws=wsa)
         torch.cuda.synchronize()
         extra["argsort_keys_per_s"] = reps * n / (time.perf_counter() - ta)
+
+    if args.lfail:
+        extra["lfail"] = lfail_leg(pcfsort)
+        log(f"lfail: {extra['lfail']['runs']} runs in {extra['lfail']['seconds']:.1f} s")
 
     if not args.no_stages:
         extra["stages"] = stages_leg(pcfsort, args.stages_n)

@@ -145,6 +145,20 @@ int pcf_level_trace(int key_type, const void *d_keys_in, const uint32_t *d_vals_
                     void *d_part_keys, uint32_t *d_part_vals, uint64_t *h_b, uint64_t *h_T,
                     uint64_t *h_sizes, uint64_t *h_scalars, void *stream);
 
+/*
+ * The bucketing-failure experiment of Sec. 4.2 (Fig. 3): for every cell c
+ * (h_cells[4c .. 4c+3] = alpha, beta, gamma, delta) and every one of `reps`
+ * fp64 arrays of n keys (device, array r at d_keys + r * n), one PCF bucketing
+ * of the whole array (Sec. 3.3: alpha samples with replacement, beta + 1
+ * equal-width bins, gamma + 1 buckets) with node seed chained over
+ * (seed, c, r, 0); h_failures[c] receives the number of arrays for which some
+ * bucket holds more than delta keys.  Parameters may exceed a sort level's
+ * (beta, gamma < 2^30).  Allocates and frees its scratch stream-ordered and
+ * synchronizes `stream`.
+ */
+int pcf_lfail_grid(const double *d_keys, size_t n, uint32_t reps, const uint32_t *h_cells,
+                   uint32_t ncells, uint64_t seed, uint32_t *h_failures, void *stream);
+
 /* ---- per-kernel profile -------------------------------------------------
  * When enabled, every later sort call records hipEvents around each of its
  * kernel launches on its stream, waits for its stream at the end, and adds

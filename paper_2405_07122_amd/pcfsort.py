@@ -38,7 +38,7 @@ EXPORTS = [
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
     "pcf_profile_enable", "pcf_profile_read", "pcf_kernel_name", "pcf_graph_stats",
-    "pcf_graph_clear", "pcf_policy_for",
+    "pcf_graph_clear", "pcf_policy_for", "pcf_lfail_grid",
 ]
 
 KERNEL_KINDS = ["setup", "range", "fit", "count", "colscan", "classify", "scatter", "lds_small",
@@ -138,6 +138,7 @@ def load(path: str = LIB_PATH):
         "pcf_graph_stats": (_INT, [ctypes.POINTER(_U64)] * 3),
         "pcf_graph_clear": (_INT, []),
         "pcf_policy_for": (_INT, [_INT, _SZ, _INT, ctypes.POINTER(Policy)]),
+        "pcf_lfail_grid": (_INT, [_VP, _SZ, _U32, _VP, _U32, _U64, _VP, _VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -276,6 +277,20 @@ def pcf_graph_stats() -> dict:
 
 def pcf_graph_clear() -> None:
     _check(load().pcf_graph_clear(), "pcf_graph_clear")
+
+
+def pcf_lfail_grid(arrays: torch.Tensor, cells, seed: int = 0, stream=None):
+    """Bucketing-failure counts (Sec. 4.2): `arrays` is a (reps, n) float64
+    device tensor; `cells` a sequence of (alpha, beta, gamma, delta).  Returns a
+    numpy array of failure counts per cell (out of reps)."""
+    import numpy as np
+    _need_cuda(arrays)
+    reps, n = arrays.shape
+    hc = np.ascontiguousarray(np.asarray(cells, dtype=np.uint32).reshape(-1, 4))
+    out = np.zeros(hc.shape[0], dtype=np.uint32)
+    _check(load().pcf_lfail_grid(_ptr(arrays), n, reps, hc.ctypes.data, hc.shape[0], seed,
+                                 out.ctypes.data, _stream(stream)), "pcf_lfail_grid")
+    return out
 
 
 def pcf_level_trace(keys: torch.Tensor, alpha: int, beta: int, gamma: int, node_seed: int,
