@@ -351,8 +351,12 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   struct {
     uint32_t total;
   } sl = {sc_lds};
+  // resident workgroups per CU: what LDS allows, capped by the registers the
+  // launch bounds give (keys only: 4 waves per SIMD = two 512-thread
+  // workgroups; with a payload or 8192-key tiles: 2 waves per SIMD = one)
   const int sc_per_cu = std::max(1, (int)(160 * 1024 / sl.total));
-  const int g_sc = cus * std::min(sc_per_cu, 2);
+  const int sc_reg_cap = (PAY || sc_ts >= 8192) ? 1 : 2;
+  const int g_sc = cus * std::min(sc_per_cu, sc_reg_cap);
   PolicyDev pd;
   pd.max_buckets = pol.max_buckets;
   pd.target_child = pol.target_child;
@@ -506,13 +510,16 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   }
   // finish every small array inside LDS
   PCF_MARK(PCF_K_LDS_SMALL, 0,
-           hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), dim3(cus * 4),
+           hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
+                              dim3(cus * K5Occ<KT, K5_SMALL_CAP, PAY>::template wg_per_cu<K5_SMALL_NT>()),
                               dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), st,
                               p, 0));
   PCF_MARK(PCF_K_LDS_BIG, 0, {
-    hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>), dim3(cus * 2),
+    hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
+                       dim3(cus * K5Occ<KT, K5_MID_CAP, PAY>::template wg_per_cu<K5_MID_NT>()),
                        dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>), st, p, 1);
-    hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), dim3(cus), dim3(K5_BIG_NT),
+    hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
+                       dim3(cus * K5Occ<KT, K5_BIG_CAP, PAY>::template wg_per_cu<K5_BIG_NT>()), dim3(K5_BIG_NT),
                        sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), st, p, 2);
   });
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status,

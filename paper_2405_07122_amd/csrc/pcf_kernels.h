@@ -103,6 +103,19 @@ struct K5Cfg {
   static constexpr uint32_t SMAX = CAP / 16 + 8;  // ranges of >= tau (>= 16) keys
 };
 
+// Occupancy targets of the in-LDS finish in waves per SIMD: 4 workgroups of 4
+// waves per CU for the 2048-key class (3 for uint64 keys with a payload, whose
+// registers need more room), 2 for 4096, 1 workgroup of 8 waves for 8192 (what
+// their LDS allows).  The launch uses exactly the resident number of
+// workgroups: items are assigned statically, so a second round of workgroups
+// would double the time of the last ones.
+template <int KT, int CAP, int PAY>
+struct K5Occ {
+  static constexpr int v = CAP <= 2048 ? ((PAY && KT == 1) ? 3 : 4) : 2;
+  template <int NT>
+  static constexpr int wg_per_cu() { return v * 4 / (NT / 64); }
+};
+
 template <int KT, int CAP, int NT, int PAY>
 struct K5Smem {
   uint64_t key[CAP];      // key images

@@ -1442,16 +1442,8 @@ __device__ void k5_level(K5Smem<KT, CAP, NT, PAY>& sm, uint32_t s, uint32_t e, u
   __syncthreads();
 }
 
-// Occupancy targets in waves per SIMD: 4 workgroups of 4 waves per CU for the
-// 2048-key class (3 with a payload, whose registers need more room), 2 for
-// 4096, 1 workgroup of 8 waves for 8192 (what their LDS allows).
-template <int CAP, int PAY>
-struct K5Occ {
-  static constexpr int v = CAP <= 2048 ? (PAY ? 3 : 4) : 2;
-};
-
 template <int KT, int CAP, int NT, int PAY>
-__global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, int cls) {
+__global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY>::v)) void k_lds_sort(Plan p, int cls) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   K5Smem<KT, CAP, NT, PAY>& sm = *reinterpret_cast<K5Smem<KT, CAP, NT, PAY>*>(lds_raw);
   constexpr int EPT = CAP / NT;
@@ -1664,22 +1656,25 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
     // payload, all reads (LDS keys and the payload, which may live in the very
     // range being written) happen before a barrier and all writes after it.
     // Keys alone in their segment (the common case) take their place at once;
-    // the others are ranked in a second, non-unrolled pass.
-    uint32_t rr[EPT], vv[EPT];
+    // the others are ranked in a second, non-unrolled pass.  With a payload,
+    // ranks and payload words are staged in LDS (seg and cnt are free by
+    // now) and written after a barrier: the payload may live in the very
+    // range being written.
     uint32_t multi = 0;  // bit kq: the key sits in a segment of several keys
 #pragma unroll
     for (int kq = 0; kq < EPT; ++kq) {
       const uint32_t i = threadIdx.x + kq * NT;
-      rr[kq] = 0xffffffffu;
-      vv[kq] = 0u;
       if (i < m) {
         const uint32_t sg = sm.seg[i];
         const uint32_t a = sg & 0xffffu, b = sg >> 16;
         if (b - a > 1) {
           multi |= 1u << kq;
+        } else if (PAY) {
+          const uint32_t ps = sm.pos[i];
+          sm.cnt[i] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
+          sm.seg[i] = a;
         } else {
-          rr[kq] = a;
-          if (!PAY) ok[a] = bits_of_img<KT>(sm.key[i]);
+          ok[a] = bits_of_img<KT>(sm.key[i]);
         }
       }
     }
@@ -1698,23 +1693,14 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
         rnk += (kq2 < k) || (kq2 == k && pq < ps);
       }
       if (PAY) {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j)
-          if (j == kq) rr[j] = rnk;
+        // a thread reads seg only at its own positions: the rank can take
+        // their place
+        sm.cnt[i] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
+        sm.seg[i] = rnk;
       } else if (rnk < m) {
         ok[rnk] = bits_of_img<KT>(k);
       } else {
         flag_internal(c);
-      }
-    }
-    if (PAY) {
-#pragma unroll
-      for (int kq = 0; kq < EPT; ++kq) {
-        const uint32_t i = threadIdx.x + kq * NT;
-        if (i < m) {
-          const uint32_t ps = sm.pos[i];
-          vv[kq] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
-        }
       }
     }
     if (PAY) {
@@ -1723,13 +1709,13 @@ __global__ __launch_bounds__(NT, (K5Occ<CAP, PAY>::v)) void k_lds_sort(Plan p, i
       for (int kq = 0; kq < EPT; ++kq) {
         const uint32_t i = threadIdx.x + kq * NT;
         if (i < m) {
-          const uint32_t rnk = rr[kq];
+          const uint32_t rnk = sm.seg[i];
           if (rnk >= m) {
             flag_internal(c);
             continue;
           }
           ok[rnk] = bits_of_img<KT>(sm.key[i]);
-          p.out_vals[it.off + rnk] = vv[kq];
+          p.out_vals[it.off + rnk] = sm.cnt[i];
         }
       }
     }
