@@ -182,8 +182,8 @@ static thread_local CallProf t_prof;
 
 // LDS-finish classes (LDS capacity and workgroup size).
 constexpr int K5_SMALL_CAP = 2048, K5_SMALL_NT = 256;
-constexpr int K5_MID_CAP = 4096, K5_MID_NT = 256;
-constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = 512;
+constexpr int K5_MID_CAP = 4096, K5_MID_NT = PCF_K5_MID_NT;
+constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = PCF_K5_BIG_NT;
 // Scatter workgroup and tile: keys only (unstable ranks) / with a payload (stable).
 constexpr int SC_NT = 512, SC_TS_KEYS = 8192, SC_TS_PAY = 4096;
 
@@ -511,15 +511,15 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   // finish every small array inside LDS
   PCF_MARK(PCF_K_LDS_SMALL, 0,
            hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
-                              dim3(cus * K5Occ<KT, K5_SMALL_CAP, PAY>::template wg_per_cu<K5_SMALL_NT>()),
+                              dim3(cus * K5Occ<KT, K5_SMALL_CAP, PAY, K5_SMALL_NT>::wg_per_cu()),
                               dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), st,
                               p, 0));
   PCF_MARK(PCF_K_LDS_BIG, 0, {
     hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
-                       dim3(cus * K5Occ<KT, K5_MID_CAP, PAY>::template wg_per_cu<K5_MID_NT>()),
+                       dim3(cus * K5Occ<KT, K5_MID_CAP, PAY, K5_MID_NT>::wg_per_cu()),
                        dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>), st, p, 1);
     hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
-                       dim3(cus * K5Occ<KT, K5_BIG_CAP, PAY>::template wg_per_cu<K5_BIG_NT>()), dim3(K5_BIG_NT),
+                       dim3(cus * K5Occ<KT, K5_BIG_CAP, PAY, K5_BIG_NT>::wg_per_cu()), dim3(K5_BIG_NT),
                        sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), st, p, 2);
   });
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status,

@@ -103,17 +103,27 @@ struct K5Cfg {
   static constexpr uint32_t SMAX = CAP / 16 + 8;  // ranges of >= tau (>= 16) keys
 };
 
-// Occupancy targets of the in-LDS finish in waves per SIMD: 4 workgroups of 4
-// waves per CU for the 2048-key class (3 for uint64 keys with a payload, whose
-// registers need more room), 2 for 4096, 1 workgroup of 8 waves for 8192 (what
-// their LDS allows).  The launch uses exactly the resident number of
-// workgroups: items are assigned statically, so a second round of workgroups
-// would double the time of the last ones.
-template <int KT, int CAP, int PAY>
+// Occupancy of the in-LDS finish: every class keeps 8 keys per thread (2048
+// keys: 256 threads, 4096: 512, 8192: 1024), which fits 4 waves per SIMD (3 for
+// uint64 keys with a payload), so a CU holds 4, 2 and 1 workgroups of the three
+// classes (what their LDS allows) with 16 waves each time.  The launch uses
+// exactly the resident number of workgroups: items are assigned statically, so
+// a second round of workgroups would double the time of the last ones.
+#ifndef PCF_K5_MID_NT
+#define PCF_K5_MID_NT 512
+#endif
+#ifndef PCF_K5_BIG_NT
+#define PCF_K5_BIG_NT 1024
+#endif
+
+template <int KT, int CAP, int PAY, int NT>
 struct K5Occ {
-  static constexpr int v = CAP <= 2048 ? ((PAY && KT == 1) ? 3 : 4) : 2;
-  template <int NT>
-  static constexpr int wg_per_cu() { return v * 4 / (NT / 64); }
+  // waves per SIMD: classes of 8 keys per thread fit 4 (uint64 with a payload:
+  // 3); 16 keys per thread need twice the registers
+  static constexpr int v = (CAP / NT <= 8) ? ((PAY && KT == 1) ? 3 : 4) : 2;
+  static constexpr int wg_per_cu() {
+    return v * 4 / (NT / 64) > 0 ? v * 4 / (NT / 64) : 1;
+  }
 };
 
 template <int KT, int CAP, int NT, int PAY>

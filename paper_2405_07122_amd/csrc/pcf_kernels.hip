@@ -1443,7 +1443,7 @@ __device__ void k5_level(K5Smem<KT, CAP, NT, PAY>& sm, uint32_t s, uint32_t e, u
 }
 
 template <int KT, int CAP, int NT, int PAY>
-__global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY>::v)) void k_lds_sort(Plan p, int cls) {
+__global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(Plan p, int cls) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   K5Smem<KT, CAP, NT, PAY>& sm = *reinterpret_cast<K5Smem<KT, CAP, NT, PAY>*>(lds_raw);
   constexpr int EPT = CAP / NT;
@@ -1747,10 +1747,10 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY>::v)) void k_lds_sort(Plan 
                                                        uint32_t);                        \
   template __global__ void k_lds_sort<KT, 2048, 256, 0>(Plan, int);                      \
   template __global__ void k_lds_sort<KT, 2048, 256, 1>(Plan, int);                      \
-  template __global__ void k_lds_sort<KT, 4096, 256, 0>(Plan, int);                      \
-  template __global__ void k_lds_sort<KT, 4096, 256, 1>(Plan, int);                      \
-  template __global__ void k_lds_sort<KT, 8192, 512, 0>(Plan, int);                      \
-  template __global__ void k_lds_sort<KT, 8192, 512, 1>(Plan, int);
+  template __global__ void k_lds_sort<KT, 4096, PCF_K5_MID_NT, 0>(Plan, int);            \
+  template __global__ void k_lds_sort<KT, 4096, PCF_K5_MID_NT, 1>(Plan, int);            \
+  template __global__ void k_lds_sort<KT, 8192, PCF_K5_BIG_NT, 0>(Plan, int);            \
+  template __global__ void k_lds_sort<KT, 8192, PCF_K5_BIG_NT, 1>(Plan, int);
 
 PCF_INST_KT(KT_F64)
 PCF_INST_KT(KT_U64)
