@@ -10,6 +10,15 @@ namespace pcf {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// Workgroups are dealt to the eight XCDs round-robin by blockIdx.  A grid-
+// stride loop over v in [0, 8*per) that visits unit (v % 8) * per + v / 8
+// gives each XCD one contiguous run of units (per = ceil(nu / 8)), so the
+// neighbouring tiles whose writes share cache lines at bucket edges meet in
+// the same L2.  The map is a bijection on [0, 8*per); values >= nu are skipped.
+__device__ __forceinline__ uint32_t xcd_unit(uint32_t v, uint32_t per) {
+  return (v & 7u) * per + (v >> 3);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = lane_id();
   return l ? (~0ull >> (64 - l)) : 0ull;

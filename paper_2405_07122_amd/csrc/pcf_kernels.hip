@@ -826,7 +826,10 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
   uint32_t* dv = io.dst_vals;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
 
-  for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+  const uint32_t per = (nu + 7) / 8;
+  for (uint32_t v = blockIdx.x; v < 8 * per; v += gridDim.x) {
+    const uint32_t u = xcd_unit(v, per);
+    if (u >= nu) continue;
     const Unit un = p.units[s][u];
     const Node& nd = p.nodes[s][un.node];
     uint32_t cb, ce;
@@ -1091,7 +1094,10 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
   uint32_t tab_node = 0xffffffffu;  // node whose table the LDS holds
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
 
-  for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+  const uint32_t per = (nu + 7) / 8;
+  for (uint32_t v = blockIdx.x; v < 8 * per; v += gridDim.x) {
+    const uint32_t u = xcd_unit(v, per);
+    if (u >= nu) continue;
     const Unit un = p.units[s][u];
     const Node& nd = p.nodes[s][un.node];
     uint32_t cb, ce;
