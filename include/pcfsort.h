@@ -190,6 +190,13 @@ typedef struct {
 } pcf_kernel_stat;
 
 int pcf_profile_enable(int on);
+/* Restricts the events to the launch kinds whose bit (1 << kind) is set in
+ * kind_mask, kinds PCF_K_SETUP .. PCF_K_LDS_BIG; the others run without events
+ * and add nothing to their counters.  Fewer events leave fewer gaps between
+ * launches, so a benchmark can time the whole call while it prices one kernel.
+ * Default: all of them.  A bit at PCF_K_RADIX_KEYS or above:
+ * PCF_ERR_INVALID_ARGUMENT (the key-count kinds are always summed). */
+int pcf_profile_select(uint32_t kind_mask);
 /* Copies PCF_K_COUNT_KINDS entries into out; reset != 0 clears the counters. */
 int pcf_profile_read(pcf_kernel_stat *out, int reset);
 const char *pcf_kernel_name(int kind);

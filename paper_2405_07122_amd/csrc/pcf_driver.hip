@@ -113,6 +113,7 @@ int device_cus() {
 // ---- opt-in per-kernel profile ---------------------------------------------
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static uint32_t g_prof_mask = (1u << PCF_K_RADIX_KEYS) - 1;  // timed kinds
 static pcf_kernel_stat g_prof[PCF_K_COUNT_KINDS];
 
 struct ProfMark {
@@ -123,11 +124,14 @@ struct ProfMark {
 // Event pairs of one call; events are pooled per thread.
 struct CallProf {
   bool on = false;
+  uint32_t mask = 0;  // kinds whose launches get events
+  bool rec = false;   // the open mark records events
   hipStream_t st = nullptr;
   std::vector<ProfMark> marks;
   size_t used = 0;
   int begin(int kind, int level) {
-    if (!on) return PCF_OK;
+    rec = on && ((mask >> kind) & 1u);
+    if (!rec) return PCF_OK;
     if (used == marks.size()) {
       ProfMark m = {kind, level, nullptr, nullptr};
       PCF_HIP(hipEventCreate(&m.a));
@@ -140,7 +144,7 @@ struct CallProf {
     return PCF_OK;
   }
   int end() {
-    if (!on) return PCF_OK;
+    if (!rec) return PCF_OK;
     PCF_HIP(hipEventRecord(marks[used].b, st));
     ++used;
     return PCF_OK;
@@ -412,6 +416,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
     t_prof.on = g_prof_on;
+    t_prof.mask = g_prof_mask;
   }
   t_prof.st = st;
   t_prof.used = 0;
@@ -818,6 +823,13 @@ size_t pcf_workspace_bytes(int key_type, size_t n, int with_payload, uint32_t nu
 int pcf_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof_on = on != 0;
+  return PCF_OK;
+}
+
+int pcf_profile_select(uint32_t kind_mask) {
+  if (kind_mask >> PCF_K_RADIX_KEYS) return PCF_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_mask = kind_mask;
   return PCF_OK;
 }
 

@@ -196,9 +196,18 @@ __global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
     uni[threadIdx.x] = (uint32_t)(base[0] + o_node);
     unb[threadIdx.x] = (uint32_t)(base[1] + o_unit);
     __syncthreads();
-    for (uint32_t j = 0; j < ROOT_NT; ++j) {
-      const uint32_t cnt = ush[j];
-      for (uint32_t i = threadIdx.x; i < cnt; i += ROOT_NT) p.units[0][unb[j] + i] = Unit{uni[j], i};
+    // this block's units are consecutive from base[1]: unit k belongs to the
+    // last root whose first unit is at or before k (a search over unb)
+    const uint32_t ub0 = (uint32_t)base[1];
+    for (uint32_t k = threadIdx.x; k < t_unit; k += ROOT_NT) {
+      uint32_t lo = 0, hi = ROOT_NT;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (unb[mid] - ub0 <= k) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t i = k - (unb[lo] - ub0);
+      if (i < ush[lo]) p.units[0][unb[lo] + i] = Unit{uni[lo], i};
     }
     __syncthreads();
     if (threadIdx.x == 0) {

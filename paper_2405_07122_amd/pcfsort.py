@@ -37,7 +37,7 @@ EXPORTS = [
     "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
-    "pcf_profile_enable", "pcf_profile_read", "pcf_kernel_name", "pcf_graph_stats",
+    "pcf_profile_enable", "pcf_profile_select", "pcf_profile_read", "pcf_kernel_name", "pcf_graph_stats",
     "pcf_graph_clear", "pcf_policy_for", "pcf_lfail_grid",
 ]
 
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH):
         "pcf_serve_destroy": (_INT, [_VP]),
         "pcf_profile_enable": (_INT, [_INT]),
         "pcf_profile_read": (_INT, [ctypes.POINTER(KernelStat), _INT]),
+        "pcf_profile_select": (_INT, [ctypes.c_uint32]),
         "pcf_kernel_name": (ctypes.c_char_p, [_INT]),
         "pcf_graph_stats": (_INT, [ctypes.POINTER(_U64)] * 3),
         "pcf_graph_clear": (_INT, []),
@@ -349,6 +350,16 @@ def policy_for(key_type: int, n: int, with_payload: bool = False) -> dict:
 
 def pcf_profile_enable(on: bool = True) -> None:
     _check(load().pcf_profile_enable(int(on)), "pcf_profile_enable")
+
+
+def pcf_profile_select(kinds=None) -> None:
+    """Record events only for the named launch kinds (None: all timed kinds)."""
+    timed = KERNEL_KINDS[:KERNEL_KINDS.index("radix_keys")]
+    kinds = timed if kinds is None else kinds
+    mask = 0
+    for k in kinds:
+        mask |= 1 << timed.index(k)
+    _check(load().pcf_profile_select(mask), "pcf_profile_select")
 
 
 def pcf_profile_read(reset: bool = False) -> dict:
