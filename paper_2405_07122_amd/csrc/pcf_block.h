@@ -10,6 +10,21 @@ namespace pcf {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// Global-memory views of generic pointers.  Key and payload arrays reach the
+// kernels through node and item records, so the compiler cannot prove their
+// address space and emits flat loads and stores; those count against the LDS
+// counter too, so every wait for an LDS result would also wait for the keys
+// prefetched for the next tile.  Through these views they become global_*
+// instructions, which count only against the vector-memory counter.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gld(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gst(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Workgroups are dealt to the eight XCDs round-robin by blockIdx.  A grid-
 // stride loop over v in [0, 8*per) that visits unit (v % 8) * per + v / 8
 // gives each XCD one contiguous run of units (per = ceil(nu / 8)), so the

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_range(Plan p) {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const uint32_t i = base + k * NT + threadIdx.x;
-        v[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+        v[k] = i < e ? __builtin_nontemporal_load(gld(src) + i) : 0ull;
       }
 #pragma unroll
       for (int k = 0; k < U; ++k) {
@@ -312,9 +312,9 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
     // range: reduce the producer's partial minima / maxima
     uint64_t lo = ~0ull, hi = 0ull;
     for (uint32_t i = threadIdx.x; i < nd.mmn; i += NT) {
-      const MinMax m = nd.mmp[i];
-      lo = m.lo < lo ? m.lo : lo;
-      hi = m.hi > hi ? m.hi : hi;
+      const uint64_t mlo = gld(nd.mmp)[i].lo, mhi = gld(nd.mmp)[i].hi;
+      lo = mlo < lo ? mlo : lo;
+      hi = mhi > hi ? mhi : hi;
     }
     block_minmax_u64<NT>(lo, hi, red64);
     if (lo == hi) {
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
           const uint32_t j = j0 + k * NT + threadIdx.x;
-          v[k] = j < alpha ? src[sample_pos(nd.seed, j, nd.len)] : 0ull;
+          v[k] = j < alpha ? gld(src)[sample_pos(nd.seed, j, nd.len)] : 0ull;
         }
 #pragma unroll
         for (int k = 0; k < SB; ++k)
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const uint32_t i = b + k * NT + threadIdx.x;
-      nv[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+      nv[k] = i < e ? __builtin_nontemporal_load(gld(src) + i) : 0ull;
     }
     for (uint32_t base = b; base < e; base += U * NT) {
 #pragma unroll
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(NT) void k_count(Plan p, int L) {
 #pragma unroll
         for (int k = 0; k < U; ++k) {
           const uint32_t i = nb2 + k * NT + threadIdx.x;
-          nv[k] = i < e ? __builtin_nontemporal_load(src + i) : 0ull;
+          nv[k] = i < e ? __builtin_nontemporal_load(gld(src) + i) : 0ull;
         }
       }
       uint32_t q[U];
@@ -848,13 +848,13 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
       // single-valued node: already in order; move it to the output if needed
       uint64_t* o = ok_ + nd.off;
       if ((const void*)o != nd.src)
-        for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) o[i] = src[i];
+        for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) gst(o)[i] = gld(src)[i];
       if (PAY) {
         uint32_t* ov = p.out_vals + nd.off;
         if (nd.vsrc == nullptr) {
           for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) ov[i] = (uint32_t)nd.rel + i;
         } else if (ov != nd.vsrc) {
-          for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) ov[i] = nd.vsrc[i];
+          for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) gst(ov)[i] = gld(nd.vsrc)[i];
         }
       }
       continue;
@@ -895,8 +895,8 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = w * PW + r * 64 + l;
-      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(src + cb + i) : 0ull;
-      if (PAY) nval[r] = cb + i < ce ? (iota ? (uint32_t)nd.rel + cb + i : vsrc[cb + i]) : 0u;
+      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(gld(src) + cb + i) : 0ull;
+      if (PAY) nval[r] = cb + i < ce ? (iota ? (uint32_t)nd.rel + cb + i : gld(vsrc)[cb + i]) : 0u;
     }
     for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
       const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
@@ -910,8 +910,8 @@ __global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, Leve
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t i = w * PW + r * 64 + l;
-          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(src + t1 + i) : 0ull;
-          if (PAY) nval[r] = t1 + i < ce ? (iota ? (uint32_t)nd.rel + t1 + i : vsrc[t1 + i]) : 0u;
+          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(gld(src) + t1 + i) : 0ull;
+          if (PAY) nval[r] = t1 + i < ce ? (iota ? (uint32_t)nd.rel + t1 + i : gld(vsrc)[t1 + i]) : 0u;
         }
       }
       // bucket and rank of every key of the tile; wave w owns keys
@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
       // single-valued node: already in order; move it to the output if needed
       uint64_t* o = ok_ + nd.off;
       if ((const void*)o != nd.src)
-        for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) o[i] = src[i];
+        for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) gst(o)[i] = gld(src)[i];
       continue;
     }
     const uint32_t nb = nd.nb, C = nd.nchunks;
@@ -1151,7 +1151,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = w * PW + r * 64 + l;
-      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(src + cb + i) : 0ull;
+      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(gld(src) + cb + i) : 0ull;
     }
     for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
       const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t i = w * PW + r * 64 + l;
-          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(src + t1 + i) : 0ull;
+          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(gld(src) + t1 + i) : 0ull;
         }
       }
       // A: bucket of every key (all table reads issued before any atomic),
@@ -1252,14 +1252,35 @@ __global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan 
       // addresses); no barrier after it: the next tile's rank phase touches
       // only tcnt and the min/max, and its bucket-start phase comes after the
       // next barrier
-      for (uint32_t i = threadIdx.x; i < tn; i += NT) {
-        const uint32_t q = sb[i];
-        const uint64_t dst = nd.off + (uint32_t)(wbase[q] + i);
-        if (dst >= nd.off + nd.len) {
-          flag_internal(c);
-          continue;
+      // (per half: the staged ids, then their write bases, then the keys,
+      // each a batch of independent LDS reads)
+      {
+        constexpr int H = R / 2 > 0 ? R / 2 : 1;
+        bool bad = false;
+#pragma unroll
+        for (int h = 0; h < R; h += H) {
+          uint32_t qd[H], wb[H];
+          uint64_t kd[H];
+#pragma unroll
+          for (int r = 0; r < H; ++r) {
+            const uint32_t i = (h + r) * NT + threadIdx.x;
+            qd[r] = i < tn ? sb[i] : 0u;
+          }
+#pragma unroll
+          for (int r = 0; r < H; ++r) wb[r] = wbase[qd[r]];
+#pragma unroll
+          for (int r = 0; r < H; ++r) kd[r] = sk[(h + r) * NT + threadIdx.x];
+#pragma unroll
+          for (int r = 0; r < H; ++r) {
+            const uint32_t i = (h + r) * NT + threadIdx.x;
+            const uint32_t rel = wb[r] + i;
+            if (i < tn) {
+              if (rel < nd.len) gst(dk)[nd.off + rel] = kd[r];
+              else bad = true;
+            }
+          }
         }
-        dk[dst] = sk[i];
+        if (bad) flag_internal(c);
       }
     }
     __syncthreads();
@@ -1483,7 +1504,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const uint32_t i = threadIdx.x + k * NT;
-      pre[k] = i < it0.len ? __builtin_nontemporal_load(s0 + i) : 0ull;
+      pre[k] = i < it0.len ? __builtin_nontemporal_load(gld(s0) + i) : 0ull;
     }
   }
   for (uint32_t ii = blockIdx.x; ii < total; ii += gridDim.x) {
@@ -1501,7 +1522,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
           const uint32_t i = threadIdx.x + k * NT;
-          pre[k] = i < nit.len ? __builtin_nontemporal_load(s1 + i) : 0ull;
+          pre[k] = i < nit.len ? __builtin_nontemporal_load(gld(s1) + i) : 0ull;
         }
       }
     } else {
@@ -1509,7 +1530,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const uint32_t i = threadIdx.x + k * NT;
-        kk[k] = i < m ? __builtin_nontemporal_load(s0 + i) : 0ull;
+        kk[k] = i < m ? __builtin_nontemporal_load(gld(s0) + i) : 0ull;
       }
     }
     // validate (roots), images, range; clear the bins
@@ -1560,7 +1581,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
         const uint32_t i = threadIdx.x + k * NT;
         if (i < m) {
           ok[i] = bits_of_img<KT>(kk[k]);
-          if (PAY) p.out_vals[it.off + i] = it.vsrc ? it.vsrc[i] : (uint32_t)it.rel + i;
+          if (PAY) p.out_vals[it.off + i] = it.vsrc ? gld(it.vsrc)[i] : (uint32_t)it.rel + i;
         }
       }
       __syncthreads();  // the range was read from red64, which the next item rewrites
@@ -1686,7 +1707,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
           multi |= 1u << kq;
         } else if (PAY) {
           const uint32_t ps = sm.pos[i];
-          sm.cnt[i] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
+          sm.cnt[i] = it.vsrc ? gld(it.vsrc)[ps] : (uint32_t)it.rel + ps;
           sm.seg[i] = a;
         } else {
           ok[a] = bits_of_img<KT>(sm.key[i]);
@@ -1710,7 +1731,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
       if (PAY) {
         // a thread reads seg only at its own positions: the rank can take
         // their place
-        sm.cnt[i] = it.vsrc ? it.vsrc[ps] : (uint32_t)it.rel + ps;
+        sm.cnt[i] = it.vsrc ? gld(it.vsrc)[ps] : (uint32_t)it.rel + ps;
         sm.seg[i] = rnk;
       } else if (rnk < m) {
         ok[rnk] = bits_of_img<KT>(k);
