@@ -280,6 +280,12 @@ __device__ __host__ inline void node_params(uint32_t len, uint32_t kind, const P
   nb = 2;
   while (nb < tgt && nb < pol.max_buckets) nb <<= 1;
   delta = root34(len);
+  // Algorithm 1 pairs gamma with delta so that an expected bucket stays far
+  // below the failure threshold; keep it at most delta / 4 here too (it
+  // matters for arrays of a few times the LDS capacity, where len / nb from
+  // the target alone would reach delta)
+  const uint32_t need = (uint32_t)((4ull * len + delta - 1) / delta);
+  while (nb < need && nb < pol.max_buckets) nb <<= 1;
   // bins and samples: bins_per_bucket / samples_per_bucket per bucket, and
   // on large arrays at least delta / 64 (a scaled form of the paper's
   // alpha = beta = floor(n^{3/4})), so that a dense region of a skewed
