@@ -189,7 +189,7 @@ constexpr int K5_SMALL_CAP = 2048, K5_SMALL_NT = 256;
 constexpr int K5_MID_CAP = 4096, K5_MID_NT = PCF_K5_MID_NT;
 constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = PCF_K5_BIG_NT;
 // Scatter workgroup and tile: keys only (unstable ranks) / with a payload (stable).
-constexpr int SC_NT = 512, SC_TS_KEYS = 8192, SC_TS_PAY = 4096;
+constexpr int SC_NT = 512, SC_TS_KEYS = 8192, SC_TS_PAY = 2048;
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -356,10 +356,10 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     uint32_t total;
   } sl = {sc_lds};
   // resident workgroups per CU: what LDS allows, capped by the registers the
-  // launch bounds give (keys only: 4 waves per SIMD = two 512-thread
-  // workgroups; with a payload or 8192-key tiles: 2 waves per SIMD = one)
+  // launch bounds give (tiles of at most 4096 keys, or 2048 with a payload:
+  // 4 waves per SIMD = two 512-thread workgroups; larger tiles: one)
   const int sc_per_cu = std::max(1, (int)(160 * 1024 / sl.total));
-  const int sc_reg_cap = (PAY || sc_ts >= 8192) ? 1 : 2;
+  const int sc_reg_cap = ((PAY && sc_ts > 2048) || sc_ts >= 8192) ? 1 : 2;
   const int g_sc = cus * std::min(sc_per_cu, sc_reg_cap);
   PolicyDev pd;
   pd.max_buckets = pol.max_buckets;

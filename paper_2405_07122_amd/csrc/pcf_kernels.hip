@@ -803,7 +803,7 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
 // workgroups resident per CU (at most 128 VGPRs); the stable variant needs
 // more registers and runs one workgroup per CU.
 template <int KT, int NT, int TS, int PAY>
-__global__ __launch_bounds__(NT, PAY ? 2 : 4) void k_scatter(Plan p, int L, LevelIO io, uint32_t max_bins,
+__global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan p, int L, LevelIO io, uint32_t max_bins,
                                                 uint32_t nbmax) {
   constexpr int NW = NT / 64;
   constexpr int PW = TS / NW;   // keys of a wave per tile
@@ -1777,7 +1777,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
                                                          uint32_t);                      \
   template __global__ void k_scatter<KT, 512, 4096, 0>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
-  template __global__ void k_scatter<KT, 512, 4096, 1>(Plan, int, LevelIO, uint32_t,     \
+  template __global__ void k_scatter<KT, 512, 1024, 1>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
   template __global__ void k_scatter<KT, 512, 2048, 1>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
