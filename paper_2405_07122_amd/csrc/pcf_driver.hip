@@ -21,13 +21,15 @@
 
 // Compile-time variants (defaults: the measured best on MI355X):
 //   PCF_KEYS_SCATTER 0: keys-only levels use the generic scatter kernel;
-//                    1: the three-barrier keys-only kernel, 4096-key tiles
-//                       (default; about 1 % faster);
-//                    2: the same with 8192-key tiles (one workgroup per CU:
-//                       25 % slower).
+//                    1: the three-barrier keys-only kernel, 4096-key tiles,
+//                       512 threads, two workgroups per CU;
+//                    2: the same with 8192-key tiles, 1024 threads, one
+//                       workgroup per CU (default: the same scatter time with
+//                       half the bucket-edge lines, and count and fit gain
+//                       from the longer work units: 2 % faster per sort).
 //   PCF_K5_CLASSES   2: LDS-finish classes <= 2048 and <= 8192 keys; 3: adds <= 4096.
 #ifndef PCF_KEYS_SCATTER
-#define PCF_KEYS_SCATTER 1
+#define PCF_KEYS_SCATTER 2
 #endif
 #ifndef PCF_K5_CLASSES
 #define PCF_K5_CLASSES 3
@@ -332,7 +334,6 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   // scatter work per level: enough units to give every workgroup a few
   const uint32_t bins_lds = std::max<uint32_t>(pol.max_bins, a.trace ? a.trace_beta : 0u);
   // keys only: the LDS-atomic scatter; with a payload: the stable one
-  static const bool big_keys_tile = getenv("PCF_SCATTER_KEYS_TILE_8K") != nullptr;
   int sc_ts;
   uint32_t sc_lds;
   if (PAY) {
@@ -343,7 +344,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
       sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY, (int)pol.model).total;
     }
   } else {
-    sc_ts = (big_keys_tile || PCF_KEYS_SCATTER == 2) ? 8192 : 4096;
+    sc_ts = PCF_KEYS_SCATTER == 2 ? 8192 : 4096;
     sc_lds = PCF_KEYS_SCATTER == 0 ? scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, 4096, 0, (int)pol.model).total
                                    : scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
     if (sc_lds > 160 * 1024 - 1024) {
@@ -469,8 +470,8 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
                            p, L, io, bins_lds, lay.nbmax);
       } else {
         if (sc_ts == 8192)
-          hipLaunchKernelGGL((k_scatter_keys<KT, SC_NT, 8192>), dim3(g_sc), dim3(SC_NT), sl.total,
-                             st, p, L, io, bins_lds, lay.nbmax);
+          hipLaunchKernelGGL((k_scatter_keys<KT, 2 * SC_NT, 8192>), dim3(g_sc), dim3(2 * SC_NT),
+                             sl.total, st, p, L, io, bins_lds, lay.nbmax);
         else
           hipLaunchKernelGGL((k_scatter_keys<KT, SC_NT, 4096>), dim3(g_sc), dim3(SC_NT), sl.total,
                              st, p, L, io, bins_lds, lay.nbmax);
@@ -577,7 +578,7 @@ static int set_attrs_typed() {
                        sc_max)) != PCF_OK)
       return r;
   } else {
-    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter_keys<KT, SC_NT, 8192>), sc_max)) !=
+    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter_keys<KT, 2 * SC_NT, 8192>), sc_max)) !=
         PCF_OK)
       return r;
     if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, 4096, 0>), sc_max)) !=

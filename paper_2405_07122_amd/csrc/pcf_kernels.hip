@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
 //   rank (LDS atomics) | wave 0: tile bucket starts, write bases, run offsets |
 //   stage in bucket order | write runs (overlaps the next tile's rank phase).
 template <int KT, int NT, int TS>
-__global__ __launch_bounds__(NT, (TS >= 8192 ? 2 : 4)) void k_scatter_keys(Plan p, int L, LevelIO io, uint32_t max_bins,
+__global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Plan p, int L, LevelIO io, uint32_t max_bins,
                                                      uint32_t nbmax) {
   constexpr int NW = NT / 64;
   constexpr int PW = TS / NW;
@@ -1771,7 +1771,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
   template __global__ void k_range<KT, 256>(Plan);                                       \
   template __global__ void k_fit<KT, 1024>(Plan, int, int);                              \
   template __global__ void k_count<KT, 512>(Plan, int);                                  \
-  template __global__ void k_scatter_keys<KT, 512, 8192>(Plan, int, LevelIO, uint32_t,   \
+  template __global__ void k_scatter_keys<KT, 1024, 8192>(Plan, int, LevelIO, uint32_t,  \
                                                          uint32_t);                      \
   template __global__ void k_scatter_keys<KT, 512, 4096>(Plan, int, LevelIO, uint32_t,   \
                                                          uint32_t);                      \
