@@ -104,26 +104,40 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* red, u
   return base + x - v;
 }
 
-// In-place scan of an LDS array a[0..n) by a workgroup of NT threads.
-// Each thread owns a contiguous run of ceil(n / NT) entries.  Returns the total.
+// In-place scan of an LDS array a[0..n) by a workgroup of NT threads.  Wave
+// w owns a contiguous run of rows of 64 entries; a row is read by the 64
+// lanes at once (consecutive words: no bank conflicts) and scanned with the
+// wave scan.  A first pass sums each wave's rows; after one barrier every
+// wave scans its rows from its prefix.  Returns the total.  Contains barriers.
 template <int NT, bool INCLUSIVE>
 __device__ uint32_t block_scan_array(uint32_t* a, uint32_t n, uint32_t* red) {
-  const uint32_t per = (n + NT - 1) / NT;
-  const uint32_t b = threadIdx.x * per;
-  const uint32_t e = (b + per < n) ? b + per : n;
+  constexpr int NW = NT / 64;
+  const int l = lane_id(), w = wave_id();
+  const uint32_t rows = (n + 63) / 64;
+  const uint32_t rpw = (rows + NW - 1) / NW;
+  const uint32_t r0 = w * rpw < rows ? w * rpw : rows;
+  const uint32_t r1 = r0 + rpw < rows ? r0 + rpw : rows;
   uint32_t s = 0;
-  for (uint32_t i = b; i < e; ++i) s += a[i];
-  uint32_t total;
-  uint32_t run = block_excl_scan<NT>(s, red, total);
-  for (uint32_t i = b; i < e; ++i) {
-    const uint32_t v = a[i];
-    if (INCLUSIVE) {
-      run += v;
-      a[i] = run;
-    } else {
-      a[i] = run;
-      run += v;
-    }
+  for (uint32_t r = r0; r < r1; ++r) {
+    const uint32_t i = r * 64 + l;
+    s += i < n ? a[i] : 0u;
+  }
+  s = wave_incl_scan(s);  // lane 63: the wave's sum
+  if (l == 63) red[w] = s;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t t = red[k];
+    run += k < w ? t : 0u;
+    total += t;
+  }
+  for (uint32_t r = r0; r < r1; ++r) {
+    const uint32_t i = r * 64 + l;
+    const uint32_t v = i < n ? a[i] : 0u;
+    const uint32_t x = wave_incl_scan(v);
+    if (i < n) a[i] = run + (INCLUSIVE ? x : x - v);
+    run += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
   }
   __syncthreads();
   return total;

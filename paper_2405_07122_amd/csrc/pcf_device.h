@@ -253,6 +253,8 @@ struct Plan {
   int32_t* cmap[2];
   uint32_t* task_node[2];
   MinMax* mmr;          // per-unit ranges of the roots (range kernel)
+  uint64_t* sbuf0;      // sample keys of a single root, gathered by the range kernel (or null)
+  uint32_t sbuf0_cap, pad0;
   uint32_t cap_nodes, cap_units, cap_aux, pad;
   unsigned long long cap_table, cap_cm;
   Item* items[3];

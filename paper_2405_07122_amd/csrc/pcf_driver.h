@@ -23,7 +23,7 @@ int hip_fail(hipError_t e, const char* what = nullptr, int line = 0);
   } while (0)
 
 struct Layout {
-  size_t ctl, tmp_keys, tmp_vals, int_keys, trace_b, mmr;
+  size_t ctl, tmp_keys, tmp_vals, int_keys, trace_b, mmr, sbuf0;
   size_t nodes[2], units[2], table[2], cm[2], mm[2], bstart[2], cmap[2], task_node[2], items[3];
   size_t total;
   uint32_t cap_nodes, cap_units, cap_aux;

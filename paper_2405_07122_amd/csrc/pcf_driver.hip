@@ -252,6 +252,8 @@ Layout make_layout(size_t n, int has_pay, uint32_t nseg, const pcf_policy& pol, 
   L.int_keys = take(int_keys ? n * 8 : 0);
   L.trace_b = take(trace_beta ? 4ull * (trace_beta + 1) : 0);
   L.mmr = take(sizeof(MinMax) * (size_t)L.cap_units);
+  // a single root's samples (plain calls): gathered while its range is read
+  L.sbuf0 = take(nseg == 1 ? 8ull * pol.max_samples : 0);
   for (int s = 0; s < 2; ++s) {
     L.nodes[s] = take(sizeof(Node) * (size_t)L.cap_nodes);
     L.units[s] = take(sizeof(Unit) * (size_t)L.cap_units);
@@ -325,6 +327,9 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     p.cap_items[k] = lay.cap_items[k];
   }
   p.mmr = reinterpret_cast<MinMax*>(ws + lay.mmr);
+  p.sbuf0 = (a.nseg == 1 && !a.trace) ? reinterpret_cast<uint64_t*>(ws + lay.sbuf0) : nullptr;
+  p.sbuf0_cap = pol.max_samples;
+  p.pad0 = 0;
   p.cap_nodes = lay.cap_nodes;
   p.cap_units = lay.cap_units;
   p.cap_aux = lay.cap_aux;

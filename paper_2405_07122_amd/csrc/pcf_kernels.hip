@@ -280,6 +280,15 @@ __global__ __launch_bounds__(NT) void k_range(Plan p) {
         }
       }
     }
+    // a single root: this unit's share of its samples (positions depend only
+    // on the node seed), so the fit reads them contiguously instead of
+    // gathering them from one workgroup
+    if (p.sbuf0 && p.ctl->lv[0].num_nodes == 1 && nd.kind != NK_RADIX && nd.alpha <= p.sbuf0_cap) {
+      const uint32_t jb = (uint32_t)(((uint64_t)nd.alpha * un.chunk) / nd.nchunks);
+      const uint32_t je = (uint32_t)(((uint64_t)nd.alpha * (un.chunk + 1)) / nd.nchunks);
+      for (uint32_t j = jb + threadIdx.x; j < je; j += NT)
+        gst(p.sbuf0)[j] = gld(src)[sample_pos(nd.seed, j, nd.len)];
+    }
     if (threadIdx.x == 0) bad_sh = 0;
     __syncthreads();
     if (bad) bad_sh = 1;
@@ -341,6 +350,8 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       for (uint32_t i = threadIdx.x; i <= beta; i += NT) hist[i] = 0u;
       __syncthreads();
       const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
+      // a single root's samples were gathered by the range kernel
+      const bool pre = L == 0 && p.sbuf0 && nn == 1 && alpha <= p.sbuf0_cap;
       // samples in batches of 8 per thread: all loads issued before any atomic
       constexpr int SB = 8;
       for (uint32_t j0 = 0; j0 < alpha; j0 += SB * NT) {
@@ -348,7 +359,8 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
           const uint32_t j = j0 + k * NT + threadIdx.x;
-          v[k] = j < alpha ? gld(src)[sample_pos(nd.seed, j, nd.len)] : 0ull;
+          v[k] = j < alpha ? (pre ? gld(p.sbuf0)[j] : gld(src)[sample_pos(nd.seed, j, nd.len)])
+                           : 0ull;
         }
 #pragma unroll
         for (int k = 0; k < SB; ++k)
