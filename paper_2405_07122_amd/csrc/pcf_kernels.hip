@@ -1158,24 +1158,28 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
     const Bucketer<KT> bk = make_bucketer<KT>(nd, tab, tab8);
 
     // software pipeline: the next tile's keys are in flight while this one
-    // is ranked, staged and written
+    // is ranked, staged and written.  Every tile issues the same vector-memory
+    // instructions (R loads, then R stores, with clamped addresses and no
+    // branch around them), so the wait for the prefetched keys is a fixed
+    // count that leaves the previous tile's stores in flight.  Range-check
+    // failures are collected and reported after the unit.
+    bool bad = false;
     uint64_t key[R], nkey[R];
+    if (cb >= ce) continue;  // (chunks of a node are never empty; the clamps below need a key)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t i = w * PW + r * 64 + l;
-      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(gld(src) + cb + i) : 0ull;
+      const uint32_t i = cb + w * PW + r * 64 + l;
+      nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
     }
     for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
       const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
 #pragma unroll
       for (int r = 0; r < R; ++r) key[r] = nkey[r];
       const uint32_t t1 = t0 + TS;
-      if (t1 < ce) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const uint32_t i = w * PW + r * 64 + l;
-          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(gld(src) + t1 + i) : 0ull;
-        }
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
+        nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
       }
       // A: bucket of every key (all table reads issued before any atomic),
       // rank inside the tile's bucket, child ranges
@@ -1186,11 +1190,8 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
         uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
-        if (q >= nb) {  // range check: cannot happen for a consistent model
-          flag_internal(c);
-          q = nb - 1;
-        }
-        qq[r] = q;
+        bad |= q >= nb;  // range check: cannot happen for a consistent model
+        qq[r] = q < nb ? q : nb - 1;
       }
       uint32_t code[R];
 #pragma unroll
@@ -1255,7 +1256,7 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
             sk[pos] = key[r];
             sb[pos] = (uint16_t)q;
           } else {
-            flag_internal(c);
+            bad = true;
           }
         }
       }
@@ -1265,36 +1266,34 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
       // only tcnt and the min/max, and its bucket-start phase comes after the
       // next barrier
       // (per half: the staged ids, then their write bases, then the keys,
-      // each a batch of independent LDS reads)
+      // each a batch of independent LDS reads).  A lane past the tile's end
+      // repeats the store of the tile's last key: same value, same address.
       {
         constexpr int H = R / 2 > 0 ? R / 2 : 1;
-        bool bad = false;
 #pragma unroll
         for (int h = 0; h < R; h += H) {
-          uint32_t qd[H], wb[H];
+          uint32_t qd[H], wb[H], ic[H];
           uint64_t kd[H];
 #pragma unroll
           for (int r = 0; r < H; ++r) {
             const uint32_t i = (h + r) * NT + threadIdx.x;
-            qd[r] = i < tn ? sb[i] : 0u;
+            ic[r] = i < tn ? i : tn - 1;
+            qd[r] = sb[ic[r]];
           }
 #pragma unroll
           for (int r = 0; r < H; ++r) wb[r] = wbase[qd[r]];
 #pragma unroll
-          for (int r = 0; r < H; ++r) kd[r] = sk[(h + r) * NT + threadIdx.x];
+          for (int r = 0; r < H; ++r) kd[r] = sk[ic[r]];
 #pragma unroll
           for (int r = 0; r < H; ++r) {
-            const uint32_t i = (h + r) * NT + threadIdx.x;
-            const uint32_t rel = wb[r] + i;
-            if (i < tn) {
-              if (rel < nd.len) gst(dk)[nd.off + rel] = kd[r];
-              else bad = true;
-            }
+            const uint32_t rel = wb[r] + ic[r];
+            bad |= rel >= nd.len;
+            gst(dk)[nd.off + (rel < nd.len ? rel : nd.len - 1)] = kd[r];
           }
         }
-        if (bad) flag_internal(c);
       }
     }
+    if (bad) flag_internal(c);
     __syncthreads();
     if (any_glb) {
       MinMax* mm = p.mm[s] + nd.cm_off;
