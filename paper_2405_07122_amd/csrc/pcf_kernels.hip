@@ -37,13 +37,8 @@
 #endif
 //   PCF_SC_BATCH_RANK  1: the scatter issues all table reads of a tile's keys
 //                      before their rank atomics.
-//   PCF_SC_BATCH_WRITE 1: the scatter reads all of a thread's staged keys
-//                      before writing any.
 #ifndef PCF_SC_BATCH_RANK
 #define PCF_SC_BATCH_RANK 1
-#endif
-#ifndef PCF_SC_BATCH_WRITE
-#define PCF_SC_BATCH_WRITE 0
 #endif
 
 namespace pcf {
@@ -901,14 +896,26 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
     const bool iota = PAY && vsrc == nullptr;
 
     // software pipeline: the next tile's keys are in flight while this one
-    // is ranked, staged and written
+    // is ranked, staged and written.  Every tile issues the same vector-memory
+    // instructions (clamped addresses, no branch around them; positions of
+    // an argsort's first level are read from the keys as a dummy and
+    // replaced), so the wait for the prefetched tile leaves the previous
+    // tile's stores in flight.  Range-check failures are reported after the
+    // unit.
+    bool bad = false;
     uint64_t key[R], nkey[R];
     uint32_t val[R], nval[R];
+    if (cb >= ce) continue;  // (chunks of a node are never empty; the clamps below need a key)
+    const uint32_t* vld = iota ? reinterpret_cast<const uint32_t*>(src) : vsrc;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t i = w * PW + r * 64 + l;
-      nkey[r] = cb + i < ce ? __builtin_nontemporal_load(gld(src) + cb + i) : 0ull;
-      if (PAY) nval[r] = cb + i < ce ? (iota ? (uint32_t)nd.rel + cb + i : gld(vsrc)[cb + i]) : 0u;
+      const uint32_t i = cb + w * PW + r * 64 + l;
+      const uint32_t ii = i < ce ? i : ce - 1;
+      nkey[r] = __builtin_nontemporal_load(gld(src) + ii);
+      if (PAY) {
+        const uint32_t lv = gld(vld)[ii];
+        nval[r] = iota ? (uint32_t)nd.rel + ii : lv;
+      }
     }
     for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
       const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
@@ -918,12 +925,14 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
         if (PAY) val[r] = nval[r];
       }
       const uint32_t t1 = t0 + TS;
-      if (t1 < ce) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const uint32_t i = w * PW + r * 64 + l;
-          nkey[r] = t1 + i < ce ? __builtin_nontemporal_load(gld(src) + t1 + i) : 0ull;
-          if (PAY) nval[r] = t1 + i < ce ? (iota ? (uint32_t)nd.rel + t1 + i : gld(vsrc)[t1 + i]) : 0u;
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
+        const uint32_t ii = i < ce ? i : ce - 1;
+        nkey[r] = __builtin_nontemporal_load(gld(src) + ii);
+        if (PAY) {
+          const uint32_t lv = gld(vld)[ii];
+          nval[r] = iota ? (uint32_t)nd.rel + ii : lv;
         }
       }
       // bucket and rank of every key of the tile; wave w owns keys
@@ -939,11 +948,8 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
       for (int r = 0; r < R; ++r) {
         const uint32_t i = w * PW + r * 64 + l;
         uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish2(qq[r], key[r]) : bk(key[r])) : 0u;
-        if (q >= nb) {  // range check: cannot happen for a consistent model
-          flag_internal(c);
-          q = nb - 1;
-        }
-        qq[r] = q;
+        bad |= q >= nb;  // range check: cannot happen for a consistent model
+        qq[r] = q < nb ? q : nb - 1;
       }
       if (any_glb) {
         // child ranges (lanes here hold unrelated buckets: few LDS conflicts)
@@ -1016,49 +1022,26 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
             if (PAY) sv[pos] = val[r];
             sb[pos] = (uint16_t)q;
           } else {
-            flag_internal(c);
+            bad = true;
           }
         }
       }
       __syncthreads();
-      // write runs: consecutive staged keys of one bucket are consecutive in HBM
-      if (PCF_SC_BATCH_WRITE) {
-        // the LDS reads of all of a thread's keys are issued first
+      // write runs: consecutive staged keys of one bucket are consecutive in
+      // HBM.  A lane past the tile's end repeats the store of the tile's last
+      // staged key (same values, same addresses).
+      {
         constexpr int WPT = TS / NT;
-        uint32_t wq[WPT], wo[WPT];
-        uint64_t wk[WPT];
 #pragma unroll
         for (int k = 0; k < WPT; ++k) {
           const uint32_t i = threadIdx.x + k * NT;
-          wq[k] = i < tn ? sb[i] : 0u;
-          wk[k] = i < tn ? sk[i] : 0ull;
-        }
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) wo[k] = runoff[wq[k]] - tstart[wq[k]];
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) {
-          const uint32_t i = threadIdx.x + k * NT;
-          if (i < tn) {
-            const uint64_t dst = nd.off + (uint32_t)(wo[k] + i);
-            if (dst >= nd.off + nd.len) {
-              flag_internal(c);
-              continue;
-            }
-            dk[dst] = wk[k];
-            if (PAY) dv[dst] = sv[i];
-          }
-        }
-      } else {
-        for (uint32_t i = threadIdx.x; i < tn; i += NT) {
-          const uint32_t q = sb[i];
-          const uint64_t dst = nd.off + runoff[q] + (i - tstart[q]);
-          const uint64_t kv = sk[i];
-          if (dst >= nd.off + nd.len) {
-            flag_internal(c);
-            continue;
-          }
-          dk[dst] = kv;
-          if (PAY) dv[dst] = sv[i];
+          const uint32_t ic = i < tn ? i : tn - 1;
+          const uint32_t q = sb[ic];
+          const uint32_t rel = runoff[q] + (ic - tstart[q]);
+          bad |= rel >= nd.len;
+          const uint64_t dst = nd.off + (rel < nd.len ? rel : nd.len - 1);
+          gst(dk)[dst] = sk[ic];
+          if (PAY) gst(dv)[dst] = sv[ic];
         }
       }
       __syncthreads();
@@ -1072,6 +1055,7 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
       }
       __syncthreads();
     }
+    if (bad) flag_internal(c);
     // this chunk's range of every child that is a node of the next level
     MinMax* mm = p.mm[s] + nd.cm_off;
     for (uint32_t q = threadIdx.x; q < nb; q += NT)
