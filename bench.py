@@ -459,17 +459,23 @@ def main():
         sys.exit(1)
 
     # timed region: events around the graded scatter launches only (events
-    # around every launch would add a gap after each of them)
+    # around every launch would add a gap after each of them).  Each call
+    # reports its data status to a device word (the asynchronous form of the
+    # call), checked after the region, so no call waits for the one before.
     pcfsort.pcf_profile_select(["scatter"])
     pcfsort.pcf_profile_enable(True)
     pcfsort.pcf_profile_read(reset=True)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws)
+        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws, d_status=status)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = pcfsort.pcf_profile_read(reset=True)
+    if int(status.item()) != 0:
+        log(f"a timed sort reported status {int(status.item())}")
+        sys.exit(1)
     # per-kernel breakdown: one more sort per array, outside the timed region
     pcfsort.pcf_profile_select(None)
     for d in dists:

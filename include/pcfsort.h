@@ -161,10 +161,13 @@ int pcf_lfail_grid(const double *d_keys, size_t n, uint32_t reps, const uint32_t
 
 /* ---- per-kernel profile -------------------------------------------------
  * When enabled, every later sort call records hipEvents around each of its
- * kernel launches on its stream, waits for its stream at the end, and adds
- * the elapsed times and the number of keys each launch processed to
- * process-wide counters.  Used by the benchmark to price each kernel against
- * the HBM roofline.  Not thread-safe with respect to concurrent calls.
+ * kernel launches on its stream and adds the elapsed times and the number of
+ * keys each launch processed to process-wide counters.  A call without a
+ * device status word waits for its stream and adds its figures at once; a
+ * call with one returns after enqueueing, and its figures are added at the
+ * calling thread's next call without a status word or its next
+ * pcf_profile_read (which waits for those calls' streams).  Used by the
+ * benchmark to price each kernel against the HBM roofline.
  */
 typedef enum {
     PCF_K_SETUP = 0,    /* control block + roots */

@@ -213,6 +213,7 @@ struct Ctl {
   uint32_t overflow;   // a capacity bound was exceeded (library bug guard); kernels
                        // read status and overflow together as one 64-bit word
   uint32_t item_count[3];
+  uint32_t item_done[3];  // items below this index were finished by an earlier pass
   uint32_t n_radix_nodes, n_fail_items, n_done_nodes;
   unsigned long long item_keys[3];  // keys in the LDS items of each class (profiling)
   // profiling: keys (summed over levels) handled by the standard sort of

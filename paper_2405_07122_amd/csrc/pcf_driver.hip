@@ -123,14 +123,34 @@ struct ProfMark {
   hipEvent_t a, b;
 };
 
-// Event pairs of one call; events are pooled per thread.
+// Event pairs of the calls of one thread; events are pooled.  A call that
+// waits for its stream folds its marks into the global counters at once; a
+// call that only enqueues (a device status word is given) leaves them
+// pending, with a copy of its control block made on the stream, until the
+// thread's next waiting call or pcf_profile_read.
 struct CallProf {
   bool on = false;
   uint32_t mask = 0;  // kinds whose launches get events
   bool rec = false;   // the open mark records events
   hipStream_t st = nullptr;
   std::vector<ProfMark> marks;
-  size_t used = 0;
+  size_t used = 0;   // marks in use (pending calls' and this call's)
+  size_t first = 0;  // this call's first mark
+  struct Pending {
+    size_t b, e;
+    Ctl* pin;
+    uint64_t n;
+    hipStream_t st;
+  };
+  std::vector<Pending> pend;
+  std::vector<Ctl*> pins;  // pinned control-block copies, one per pending call
+  void start(hipStream_t s, bool on_, uint32_t mask_) {
+    st = s;
+    on = on_;
+    mask = mask_;
+    if (pend.empty()) used = 0;
+    first = used;
+  }
   int begin(int kind, int level) {
     rec = on && ((mask >> kind) & 1u);
     if (!rec) return PCF_OK;
@@ -151,14 +171,13 @@ struct CallProf {
     ++used;
     return PCF_OK;
   }
-  // after the stream is synchronized: fold the marks into the global counters
-  int commit(const Ctl& hc, uint64_t n) {
-    if (!on) return PCF_OK;
+  // marks [b, e) of a finished call, with its control block
+  int fold(size_t b, size_t e, const Ctl& hc, uint64_t n) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof[PCF_K_RADIX_KEYS].keys += (double)hc.radix_keys;
     g_prof[PCF_K_BITONIC_KEYS].keys += (double)hc.bitonic_keys;
     g_prof[PCF_K_SINGLE_KEYS].keys += (double)hc.single_keys;
-    for (size_t i = 0; i < used; ++i) {
+    for (size_t i = b; i < e; ++i) {
       float ms = 0.f;
       PCF_HIP(hipEventElapsedTime(&ms, marks[i].a, marks[i].b));
       const int k = marks[i].kind, L = marks[i].level;
@@ -171,8 +190,39 @@ struct CallProf {
       g_prof[k].ms += ms;
       g_prof[k].keys += keys;
     }
-    used = 0;
     return PCF_OK;
+  }
+  // this call only enqueues: copy its control block on the stream, fold later
+  int defer(const Ctl* dctl, uint64_t n) {
+    if (!on) return PCF_OK;
+    if (pend.size() == pins.size()) {
+      Ctl* pin = nullptr;
+      PCF_HIP(hipHostMalloc(reinterpret_cast<void**>(&pin), sizeof(Ctl), hipHostMallocPortable));
+      pins.push_back(pin);
+    }
+    Ctl* pin = pins[pend.size()];
+    PCF_HIP(hipMemcpyAsync(pin, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    pend.push_back({first, used, pin, n, st});
+    return PCF_OK;
+  }
+  // waits for the pending calls' streams and folds their marks
+  int drain() {
+    for (const Pending& pc : pend) PCF_HIP(hipStreamSynchronize(pc.st));
+    for (const Pending& pc : pend) {
+      const int r = fold(pc.b, pc.e, *pc.pin, pc.n);
+      if (r != PCF_OK) return r;
+    }
+    pend.clear();
+    used = first = 0;
+    return PCF_OK;
+  }
+  // after this call's stream is synchronized
+  int commit(const Ctl& hc, uint64_t n) {
+    if (on) {
+      const int r = fold(first, used, hc, n);
+      if (r != PCF_OK) return r;
+    }
+    return drain();
   }
 };
 static thread_local CallProf t_prof;
@@ -292,10 +342,35 @@ static int chain_levels(uint64_t n, uint32_t cap) {
   return std::min(planned_levels(n, cap) + 9, MAX_LEVELS - 1);
 }
 
-// Enqueues one sort on a.stream.  fixed_levels == 0: the level loop reads back
-// the next level's size once the planned levels have run; fixed_levels > 0:
-// exactly that many levels are launched with no host synchronization (empty
-// levels exit at once), so the launches can be captured into a graph.
+// A pinned copy of the control block and an event, per device and thread,
+// for reading the block back without draining the stream.  Both live until
+// the process ends.
+static int ctl_readback_slot(Ctl** pin, hipEvent_t* ev) {
+  struct Slot {
+    Ctl* pin = nullptr;
+    hipEvent_t ev = nullptr;
+  };
+  static thread_local Slot slots[16];
+  int dev = 0;
+  PCF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 16) return PCF_ERR_UNSUPPORTED;
+  Slot& sl = slots[dev];
+  if (!sl.pin)
+    PCF_HIP(hipHostMalloc(reinterpret_cast<void**>(&sl.pin), sizeof(Ctl), hipHostMallocPortable));
+  if (!sl.ev) PCF_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  *pin = sl.pin;
+  *ev = sl.ev;
+  return PCF_OK;
+}
+
+// Enqueues one sort on a.stream.  fixed_levels == 0: the planned levels run
+// without host reads; a copy of the control block is then read back while
+// the LDS finish of the items so far already runs, and only if a further
+// level holds nodes (failed buckets of skewed inputs) do more levels follow,
+// each with a host read, and a second finish pass for their items.
+// fixed_levels > 0: exactly that many levels are launched with no host
+// synchronization (empty levels exit at once), so the launches can be
+// captured into a graph.
 template <int KT, int PAY>
 static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
                      int fixed_levels) {
@@ -421,11 +496,8 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
 
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    t_prof.on = g_prof_on;
-    t_prof.mask = g_prof_mask;
+    t_prof.start(st, g_prof_on, g_prof_mask);
   }
-  t_prof.st = st;
-  t_prof.used = 0;
   PCF_MARK(PCF_K_SETUP, 0, {
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, p);
     hipLaunchKernelGGL(k_roots, dim3(1), dim3(1024), 0, st, p, ra);
@@ -438,18 +510,8 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   const int planned = a.trace ? 1 : planned_levels(a.n, pol.lds_cap);
   int levels = 0;
   Ctl hc;
-  for (int L = 0; L < planned || true; ++L) {
-    if (fixed_levels > 0) {
-      if (L >= fixed_levels) break;
-    } else if (L >= planned) {
-      // read back the next level's size only once the planned levels have run
-      PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-      PCF_HIP(hipStreamSynchronize(st));
-      if (hc.status) return hc.status;
-      if (hc.overflow) return overflow_status(hc.overflow);
-      if (hc.lv[L].num_nodes == 0 || a.trace) break;
-      if (L >= MAX_LEVELS - 1) return PCF_ERR_OUT_OF_MEMORY;
-    }
+  // one level of fit, count, column scan, classify and scatter
+  auto level = [&](int L) -> int {
     LevelIO io;
     io.dst_keys = kdst[L & 1];
     io.dst_vals = vdst[L & 1];
@@ -484,10 +546,58 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     });
     PCF_HIP(hipGetLastError());
     ++levels;
+    return PCF_OK;
+  };
+  // one pass of the LDS finish over the items listed since the last pass,
+  // then the status word
+  auto finish = [&](int check_level) -> int {
+    // finish every small array inside LDS
+    PCF_MARK(PCF_K_LDS_SMALL, 0,
+             hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
+                                dim3(cus * K5Occ<KT, K5_SMALL_CAP, PAY, K5_SMALL_NT>::wg_per_cu()),
+                                dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), st,
+                                p, 0));
+    PCF_MARK(PCF_K_LDS_BIG, 0, {
+      hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
+                         dim3(cus * K5Occ<KT, K5_MID_CAP, PAY, K5_MID_NT>::wg_per_cu()),
+                         dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>), st, p, 1);
+      hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
+                         dim3(cus * K5Occ<KT, K5_BIG_CAP, PAY, K5_BIG_NT>::wg_per_cu()), dim3(K5_BIG_NT),
+                         sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), st, p, 2);
+    });
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status, check_level);
+    PCF_HIP(hipGetLastError());
+    return PCF_OK;
+  };
+  // the control block as it stands after the work enqueued so far (a pinned
+  // copy on the stream, waited for through an event)
+  auto readback = [&]() -> int {
+    Ctl* pin = nullptr;
+    hipEvent_t ev = nullptr;
+    const int rr = ctl_readback_slot(&pin, &ev);
+    if (rr != PCF_OK) return rr;
+    PCF_HIP(hipMemcpyAsync(pin, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    PCF_HIP(hipEventRecord(ev, st));
+    PCF_HIP(hipEventSynchronize(ev));
+    std::memcpy(&hc, pin, sizeof(Ctl));
+    return PCF_OK;
+  };
+  int r = PCF_OK;
+  if (fixed_levels > 0) {
+    // a fixed chain (graph capture): every level, one finish pass, no host reads
+    for (int L = 0; L < fixed_levels; ++L)
+      if ((r = level(L)) != PCF_OK) return r;
+    if (a.levels_run) *a.levels_run = (uint32_t)levels;
+    return finish(fixed_levels);
   }
-  if (a.levels_run) *a.levels_run = (uint32_t)levels;
   if (a.trace) {
-    t_prof.used = 0;
+    // one level with the caller's parameters, then its model and partition
+    if ((r = level(0)) != PCF_OK) return r;
+    if (a.levels_run) *a.levels_run = (uint32_t)levels;
+    if ((r = readback()) != PCF_OK) return r;
+    if (hc.status) return hc.status;
+    if (hc.overflow) return overflow_status(hc.overflow);
+    t_prof.used = t_prof.first;  // a trace level is not profiled
     // the level's model and bucket sizes for the caller
     Node nd;
     PCF_HIP(hipMemcpyAsync(&nd, p.nodes[0], sizeof(Node), hipMemcpyDeviceToHost, st));
@@ -519,24 +629,37 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     }
     return PCF_OK;
   }
-  // finish every small array inside LDS
-  PCF_MARK(PCF_K_LDS_SMALL, 0,
-           hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
-                              dim3(cus * K5Occ<KT, K5_SMALL_CAP, PAY, K5_SMALL_NT>::wg_per_cu()),
-                              dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), st,
-                              p, 0));
-  PCF_MARK(PCF_K_LDS_BIG, 0, {
-    hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
-                       dim3(cus * K5Occ<KT, K5_MID_CAP, PAY, K5_MID_NT>::wg_per_cu()),
-                       dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>), st, p, 1);
-    hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
-                       dim3(cus * K5Occ<KT, K5_BIG_CAP, PAY, K5_BIG_NT>::wg_per_cu()), dim3(K5_BIG_NT),
-                       sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), st, p, 2);
-  });
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status,
-                     fixed_levels > 0 ? fixed_levels : -1);
+  // the planned levels run without host reads; the control block is then
+  // copied back while the LDS finish of the items so far already runs, so
+  // the device does not wait for the host's decision on further levels
+  for (int L = 0; L < planned; ++L)
+    if ((r = level(L)) != PCF_OK) return r;
+  Ctl* pin = nullptr;
+  hipEvent_t ev = nullptr;
+  if ((r = ctl_readback_slot(&pin, &ev)) != PCF_OK) return r;
+  PCF_HIP(hipMemcpyAsync(pin, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  PCF_HIP(hipEventRecord(ev, st));
+  if ((r = finish(-1)) != PCF_OK) return r;
+  PCF_HIP(hipEventSynchronize(ev));
+  std::memcpy(&hc, pin, sizeof(Ctl));
+  if (hc.status) return hc.status;
+  if (hc.overflow) return overflow_status(hc.overflow);
+  if (hc.lv[planned].num_nodes != 0) {
+    // rare (failed buckets of skewed inputs): more levels, one host read each
+    for (int L = planned;; ++L) {
+      if (L >= MAX_LEVELS - 1) return PCF_ERR_OUT_OF_MEMORY;
+      if ((r = level(L)) != PCF_OK) return r;
+      if ((r = readback()) != PCF_OK) return r;
+      if (hc.status) return hc.status;
+      if (hc.overflow) return overflow_status(hc.overflow);
+      if (hc.lv[L + 1].num_nodes == 0) break;
+    }
+    if ((r = finish(-1)) != PCF_OK) return r;
+  }
+  if (a.levels_run) *a.levels_run = (uint32_t)levels;
   PCF_HIP(hipGetLastError());
-  if (fixed_levels > 0 || (a.d_status && !t_prof.on)) return PCF_OK;
+  if (fixed_levels > 0) return PCF_OK;
+  if (a.d_status) return t_prof.defer(p.ctl, a.n);  // errors reach the status word
   PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   PCF_HIP(hipStreamSynchronize(st));
   {
@@ -841,6 +964,10 @@ int pcf_profile_select(uint32_t kind_mask) {
 
 int pcf_profile_read(pcf_kernel_stat* out, int reset) {
   if (!out) return PCF_ERR_INVALID_ARGUMENT;
+  {
+    const int r = t_prof.drain();  // this thread's calls that only enqueued
+    if (r != PCF_OK) return r;
+  }
   std::lock_guard<std::mutex> g(g_prof_mu);
   for (int i = 0; i < PCF_K_COUNT_KINDS; ++i) out[i] = g_prof[i];
   if (reset) std::memset(g_prof, 0, sizeof(g_prof));

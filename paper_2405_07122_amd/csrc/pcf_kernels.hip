@@ -72,6 +72,9 @@ __global__ void k_finish(Plan p, int32_t* d_status, int check_level) {
   Ctl* c = p.ctl;
   if (check_level >= 0 && check_level < MAX_LEVELS && c->lv[check_level].num_nodes != 0)
     atomicOr(&c->overflow, OVF_CAPACITY);
+  // the LDS items listed so far are finished: a later pass starts after them
+  for (int k = 0; k < 3; ++k)
+    c->item_done[k] = c->item_count[k] < p.cap_items[k] ? c->item_count[k] : p.cap_items[k];
   int32_t s = c->status;
   const uint32_t ovf = c->overflow;
   if (s == 0 && ovf) s = (ovf & OVF_INTERNAL) ? ERR_HIP : ERR_OUT_OF_MEMORY;
@@ -1485,6 +1488,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
   if (!ctl_ok(c)) return;
   const uint32_t total = c->item_count[cls] < p.cap_items[cls] ? c->item_count[cls]
                                                                 : p.cap_items[cls];
+  const uint32_t first = c->item_done[cls];  // items of earlier passes are done
   const uint32_t tau = p.pol.tau;
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
   const int l = lane_id(), w = wave_id();
@@ -1493,8 +1497,8 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
   // a same-address atomic per item); with PCF_K5_PREFETCH the next item's
   // keys are loaded into registers while this one is sorted
   uint64_t pre[EPT];
-  if (PCF_K5_PREFETCH && blockIdx.x < total) {
-    const Item it0 = p.items[cls][blockIdx.x];
+  if (PCF_K5_PREFETCH && first + blockIdx.x < total) {
+    const Item it0 = p.items[cls][first + blockIdx.x];
     const uint64_t* s0 = reinterpret_cast<const uint64_t*>(it0.src);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
@@ -1502,7 +1506,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
       pre[k] = i < it0.len ? __builtin_nontemporal_load(gld(s0) + i) : 0ull;
     }
   }
-  for (uint32_t ii = blockIdx.x; ii < total; ii += gridDim.x) {
+  for (uint32_t ii = first + blockIdx.x; ii < total; ii += gridDim.x) {
     const Item it = p.items[cls][ii];
     const uint32_t m = it.len;
     done_keys += m;
