@@ -5,8 +5,8 @@ oracle (through the tests) and the HIP library consume the arrays it returns,
 so the two sides always sort the same bytes.
 
 Distributions (Sec. 4, setup paragraph): Uniform(0, 1), Normal(0, 1),
-Exponential(1), LogNormal(0, 1); this build adds chi-squared(4) and an
-8-Gaussian mixture.  The paper's real datasets (App. B) are not available;
+Exponential(1), LogNormal(0, 1); chi-squared(4) and an
+8-Gaussian mixture are added.  The paper's real datasets (App. B) are not available;
 three uint64 generators stand in for their shapes: heavy duplicates (Zipf),
 clustered identifiers and bursty timestamps.  Every fp64 key is finite and
 canonicalised with ``x + 0.0`` so that -0.0 never occurs.
