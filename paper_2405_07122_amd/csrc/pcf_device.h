@@ -184,7 +184,8 @@ struct Node {
   uint32_t nb, nbits, beta, alpha, delta;
   uint32_t iota;            // payload is the position inside the segment
   // filled by the fit kernel
-  uint32_t state, shift, halves, pad;
+  uint32_t state, shift, halves;
+  uint32_t logd;             // radix node: digits on a log scale (keys spread over many octaves)
   uint64_t min_img, max_img;
   double scale;
 };

@@ -306,6 +306,11 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
   __shared__ uint32_t hist[MAX_BINS + 1];
   __shared__ uint32_t red[NT / 64 + 1];
   __shared__ uint64_t red64[2 * NT / 64];
+  constexpr uint32_t RS = 256;  // samples that choose a radix node's digit scale
+  __shared__ uint64_t rs_x[RS];
+  __shared__ uint32_t rs_cnt[RS];
+  __shared__ uint64_t rs_q[2];
+  __shared__ uint32_t rs_dom[2];
   const int s = L & 1;
   Ctl* c = p.ctl;
   const uint32_t nn = c->lv[L].num_nodes;
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       __syncthreads();
       continue;
     }
-    uint32_t kind = nd.kind, shift = 0;
+    uint32_t kind = nd.kind, shift = 0, logd = 0;
     const uint32_t nb = nd.nb, beta = nd.beta, alpha = nd.alpha;
     BinFn f = {};
     if (kind != NK_RADIX && !bin_setup<KT>(f, lo, hi, beta)) kind = NK_RADIX;  // scale not finite
@@ -344,6 +349,54 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       const uint32_t top = 63u - (uint32_t)__clzll((long long)range);
       const uint32_t nbits = nd.nbits;
       shift = top + 1 > nbits ? top + 1 - nbits : 0u;
+      if (top >= 16 && nd.len >= RS) {
+        // RS samples: if most of them share one digit and, inside it, span
+        // eight octaves or more between their 10th and 90th percentiles,
+        // the keys spread over scales (clusters at log-uniform offsets) and
+        // digits on a log scale split them; a point mass or a narrow range
+        // keeps the linear digits
+        const uint32_t t = threadIdx.x;
+        if (t < RS) rs_cnt[t] = 0u;
+        __syncthreads();
+        uint64_t xs = 0;
+        uint32_t dg = 0;
+        if (t < RS) {
+          xs = img_of<KT>(gld(reinterpret_cast<const uint64_t*>(nd.src))[sample_pos(nd.seed, t, nd.len)]) - lo;
+          dg = (uint32_t)(xs >> shift);
+          rs_x[t] = xs;
+          atomicAdd(&rs_cnt[dg], 1u);
+        }
+        __syncthreads();
+        if (t == 0) {
+          uint32_t best = 0, bc = 0;
+          for (uint32_t d = 0; d < RS; ++d)
+            if (rs_cnt[d] > bc) {
+              bc = rs_cnt[d];
+              best = d;
+            }
+          rs_dom[0] = best;
+          rs_dom[1] = bc;
+          rs_q[0] = rs_q[1] = 0;
+        }
+        __syncthreads();
+        const uint32_t dom = rs_dom[0], dcnt = rs_dom[1];
+        if (dcnt >= RS / 2) {
+          if (t < RS && dg == dom) {
+            uint32_t rk = 0;  // rank among the dominant digit's samples (ties by index)
+            for (uint32_t j = 0; j < RS; ++j) {
+              const uint64_t xj = rs_x[j];
+              rk += ((uint32_t)(xj >> shift) == dom) && (xj < xs || (xj == xs && j < t));
+            }
+            if (rk == dcnt / 10) rs_q[0] = xs;
+            if (rk == dcnt - 1 - dcnt / 10) rs_q[1] = xs;
+          }
+          __syncthreads();
+          const uint64_t q0 = rs_q[0], q1 = rs_q[1];
+          const uint32_t e0 = q0 ? 64u - (uint32_t)__clzll((long long)q0) : 0u;
+          const uint32_t e1 = q1 ? 64u - (uint32_t)__clzll((long long)q1) : 0u;
+          logd = e1 >= e0 + 8 ? 1u : 0u;
+        }
+      }
     } else {
       for (uint32_t i = threadIdx.x; i <= beta; i += NT) hist[i] = 0u;
       __syncthreads();
@@ -388,6 +441,7 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       nd.kind = kind;
       nd.state = NS_ACTIVE;
       nd.shift = shift;
+      nd.logd = logd;
       nd.halves = f.halves;
       nd.scale = f.s;
       nd.min_img = lo;
@@ -406,12 +460,20 @@ struct Bucketer {
   uint64_t lo_img;
   uint32_t shift;
   uint32_t radix;
+  uint32_t logd;        // radix digits on a log scale
   uint32_t narrow;      // T held as bytes (at most 256 buckets)
   uint32_t spline;      // the table holds prefix counts b_i (App. A.5)
   double alpha, gamma;  // spline: sample count and last bucket index
   const void* tab;      // LDS copy of T (or of b for the spline)
   __device__ __forceinline__ uint32_t index(uint64_t bits) const {
-    if (radix) return (uint32_t)((img_of<KT>(bits) - lo_img) >> shift);
+    if (radix) {
+      const uint64_t x = img_of<KT>(bits) - lo_img;
+      if (!logd) return (uint32_t)(x >> shift);
+      // four digits per octave: the octave, then the two bits after the
+      // leading one (monotone in x; at most 251)
+      const uint32_t e = x ? 64u - (uint32_t)__clzll((long long)x) : 0u;
+      return e <= 2 ? (uint32_t)x : (e - 2) * 4 + (uint32_t)((x >> (e - 3)) & 3u);
+    }
     return bin_of<KT>(f, bits);
   }
   __device__ __forceinline__ uint32_t finish(uint32_t idx) const {
@@ -454,6 +516,7 @@ __device__ __forceinline__ Bucketer<KT> make_bucketer(const Node& nd, const void
   Bucketer<KT> bk;
   bk.lo_img = nd.min_img;
   bk.shift = nd.shift;
+  bk.logd = nd.logd;
   bk.radix = nd.kind == NK_RADIX;
   bk.spline = nd.kind == NK_SPLINE;
   bk.narrow = (narrow && !bk.spline) ? 1u : 0u;
