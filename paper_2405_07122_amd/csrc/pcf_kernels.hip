@@ -971,29 +971,13 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
     bool bad = false;
     uint64_t key[R], nkey[R];
     uint32_t val[R], nval[R];
-    if (cb >= ce) continue;  // (chunks of a node are never empty; the clamps below need a key)
-    const uint32_t* vld = iota ? reinterpret_cast<const uint32_t*>(src) : vsrc;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = cb + w * PW + r * 64 + l;
-      const uint32_t ii = i < ce ? i : ce - 1;
-      nkey[r] = __builtin_nontemporal_load(gld(src) + ii);
-      if (PAY) {
-        const uint32_t lv = gld(vld)[ii];
-        nval[r] = iota ? (uint32_t)nd.rel + ii : lv;
-      }
-    }
-    for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
-      const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
+    // (chunks of a node are never empty; the clamped addresses below need a
+    // key: an empty chunk skips the tiles and leaves neutral ranges)
+    if (cb < ce) {
+      const uint32_t* vld = iota ? reinterpret_cast<const uint32_t*>(src) : vsrc;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        key[r] = nkey[r];
-        if (PAY) val[r] = nval[r];
-      }
-      const uint32_t t1 = t0 + TS;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
+        const uint32_t i = cb + w * PW + r * 64 + l;
         const uint32_t ii = i < ce ? i : ce - 1;
         nkey[r] = __builtin_nontemporal_load(gld(src) + ii);
         if (PAY) {
@@ -1001,125 +985,144 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
           nval[r] = iota ? (uint32_t)nd.rel + ii : lv;
         }
       }
-      // bucket and rank of every key of the tile; wave w owns keys
-      // [w*PW, (w+1)*PW), round r lane l
-      uint32_t code[R];  // bucket << 16 | rank
-      uint16_t* wc = wcnt + w * nb;
-      uint32_t qq[R];
-      if (PCF_SC_BATCH_RANK) {
+      for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
+        const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
-      }
+        for (int r = 0; r < R; ++r) {
+          key[r] = nkey[r];
+          if (PAY) val[r] = nval[r];
+        }
+        const uint32_t t1 = t0 + TS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish2(qq[r], key[r]) : bk(key[r])) : 0u;
-        bad |= q >= nb;  // range check: cannot happen for a consistent model
-        qq[r] = q < nb ? q : nb - 1;
-      }
-      if (any_glb) {
-        // child ranges (lanes here hold unrelated buckets: few LDS conflicts)
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
+          const uint32_t ii = i < ce ? i : ce - 1;
+          nkey[r] = __builtin_nontemporal_load(gld(src) + ii);
+          if (PAY) {
+            const uint32_t lv = gld(vld)[ii];
+            nval[r] = iota ? (uint32_t)nd.rel + ii : lv;
+          }
+        }
+        // bucket and rank of every key of the tile; wave w owns keys
+        // [w*PW, (w+1)*PW), round r lane l
+        uint32_t code[R];  // bucket << 16 | rank
+        uint16_t* wc = wcnt + w * nb;
+        uint32_t qq[R];
+        if (PCF_SC_BATCH_RANK) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t i = w * PW + r * 64 + l;
-          if (i < tn && cmapf[qq[r]]) {
-            const unsigned long long im = img_of<KT>(key[r]);
-            atomicMin(&mmlo[qq[r]], im);
-            atomicMax(&mmhi[qq[r]], im);
+          uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish2(qq[r], key[r]) : bk(key[r])) : 0u;
+          bad |= q >= nb;  // range check: cannot happen for a consistent model
+          qq[r] = q < nb ? q : nb - 1;
+        }
+        if (any_glb) {
+          // child ranges (lanes here hold unrelated buckets: few LDS conflicts)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const uint32_t i = w * PW + r * 64 + l;
+            if (i < tn && cmapf[qq[r]]) {
+              const unsigned long long im = img_of<KT>(key[r]);
+              atomicMin(&mmlo[qq[r]], im);
+              atomicMax(&mmhi[qq[r]], im);
+            }
           }
         }
-      }
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        const bool valid = i < tn;
-        const uint32_t q = qq[r];
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          const bool valid = i < tn;
+          const uint32_t q = qq[r];
+          if (PAY) {
+            // stable: rank among equal buckets in lane order, per-wave counters
+            const uint64_t act = __ballot(valid);
+            const uint64_t peers = wave_match(q, nbits, act);
+            const uint32_t rk = (uint32_t)__popcll(peers & lanemask_lt());
+            uint32_t base = 0;
+            if (valid) base = wc[q];
+            if (valid && rk == 0) wc[q] = (uint16_t)(base + (uint32_t)__popcll(peers));
+            code[r] = (q << 16) | (base + rk);
+          } else {
+            // keys only: any order inside a bucket is the same output
+            const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
+            const uint64_t act = __ballot(valid);
+            uint32_t rk = 0;
+            if (act == ~0ull && __all(q == q0)) {
+              uint32_t b0 = 0;
+              if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
+              rk = __builtin_amdgcn_readfirstlane(b0) + l;
+            } else if (valid) {
+              rk = atomicAdd(&tcnt[q], 1u);
+            }
+            code[r] = (q << 16) | rk;
+          }
+        }
+        __syncthreads();
         if (PAY) {
-          // stable: rank among equal buckets in lane order, per-wave counters
-          const uint64_t act = __ballot(valid);
-          const uint64_t peers = wave_match(q, nbits, act);
-          const uint32_t rk = (uint32_t)__popcll(peers & lanemask_lt());
-          uint32_t base = 0;
-          if (valid) base = wc[q];
-          if (valid && rk == 0) wc[q] = (uint16_t)(base + (uint32_t)__popcll(peers));
-          code[r] = (q << 16) | (base + rk);
-        } else {
-          // keys only: any order inside a bucket is the same output
-          const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
-          const uint64_t act = __ballot(valid);
-          uint32_t rk = 0;
-          if (act == ~0ull && __all(q == q0)) {
-            uint32_t b0 = 0;
-            if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
-            rk = __builtin_amdgcn_readfirstlane(b0) + l;
-          } else if (valid) {
-            rk = atomicAdd(&tcnt[q], 1u);
-          }
-          code[r] = (q << 16) | rk;
-        }
-      }
-      __syncthreads();
-      if (PAY) {
-        // per bucket: wave offsets (exclusive over waves) and tile counts
-        for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-          uint32_t run = 0;
+          // per bucket: wave offsets (exclusive over waves) and tile counts
+          for (uint32_t q = threadIdx.x; q < nb; q += NT) {
+            uint32_t run = 0;
 #pragma unroll
-          for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t v = wcnt[ww * nb + q];
-            wcnt[ww * nb + q] = (uint16_t)run;
-            run += v;
+            for (int ww = 0; ww < NW; ++ww) {
+              const uint32_t v = wcnt[ww * nb + q];
+              wcnt[ww * nb + q] = (uint16_t)run;
+              run += v;
+            }
+            tcnt[q] = run;
           }
-          tcnt[q] = run;
+          __syncthreads();
+        }
+        for (uint32_t q = threadIdx.x; q < nb; q += NT) tstart[q] = tcnt[q];
+        __syncthreads();
+        block_scan_array<NT, false>(tstart, nb, red);
+        // stage keys in bucket order
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          if (i < tn) {
+            const uint32_t q = code[r] >> 16;
+            const uint32_t pos = tstart[q] + (PAY ? wc[q] : 0u) + (code[r] & 0xffffu);
+            if (pos < (uint32_t)TS) {
+              sk[pos] = key[r];
+              if (PAY) sv[pos] = val[r];
+              sb[pos] = (uint16_t)q;
+            } else {
+              bad = true;
+            }
+          }
+        }
+        __syncthreads();
+        // write runs: consecutive staged keys of one bucket are consecutive in
+        // HBM.  A lane past the tile's end repeats the store of the tile's last
+        // staged key (same values, same addresses).
+        {
+          constexpr int WPT = TS / NT;
+#pragma unroll
+          for (int k = 0; k < WPT; ++k) {
+            const uint32_t i = threadIdx.x + k * NT;
+            const uint32_t ic = i < tn ? i : tn - 1;
+            const uint32_t q = sb[ic];
+            const uint32_t rel = runoff[q] + (ic - tstart[q]);
+            bad |= rel >= nd.len;
+            const uint64_t dst = nd.off + (rel < nd.len ? rel : nd.len - 1);
+            gst(dk)[dst] = sk[ic];
+            if (PAY) gst(dv)[dst] = sv[ic];
+          }
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < nb; q += NT) {
+          runoff[q] += tcnt[q];
+          tcnt[q] = 0u;
+          if (PAY) {
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) wcnt[ww * nb + q] = 0;
+          }
         }
         __syncthreads();
       }
-      for (uint32_t q = threadIdx.x; q < nb; q += NT) tstart[q] = tcnt[q];
-      __syncthreads();
-      block_scan_array<NT, false>(tstart, nb, red);
-      // stage keys in bucket order
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        if (i < tn) {
-          const uint32_t q = code[r] >> 16;
-          const uint32_t pos = tstart[q] + (PAY ? wc[q] : 0u) + (code[r] & 0xffffu);
-          if (pos < (uint32_t)TS) {
-            sk[pos] = key[r];
-            if (PAY) sv[pos] = val[r];
-            sb[pos] = (uint16_t)q;
-          } else {
-            bad = true;
-          }
-        }
-      }
-      __syncthreads();
-      // write runs: consecutive staged keys of one bucket are consecutive in
-      // HBM.  A lane past the tile's end repeats the store of the tile's last
-      // staged key (same values, same addresses).
-      {
-        constexpr int WPT = TS / NT;
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) {
-          const uint32_t i = threadIdx.x + k * NT;
-          const uint32_t ic = i < tn ? i : tn - 1;
-          const uint32_t q = sb[ic];
-          const uint32_t rel = runoff[q] + (ic - tstart[q]);
-          bad |= rel >= nd.len;
-          const uint64_t dst = nd.off + (rel < nd.len ? rel : nd.len - 1);
-          gst(dk)[dst] = sk[ic];
-          if (PAY) gst(dv)[dst] = sv[ic];
-        }
-      }
-      __syncthreads();
-      for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-        runoff[q] += tcnt[q];
-        tcnt[q] = 0u;
-        if (PAY) {
-#pragma unroll
-          for (int ww = 0; ww < NW; ++ww) wcnt[ww * nb + q] = 0;
-        }
-      }
-      __syncthreads();
     }
     if (bad) flag_internal(c);
     // this chunk's range of every child that is a node of the next level
@@ -1215,130 +1218,133 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
     // failures are collected and reported after the unit.
     bool bad = false;
     uint64_t key[R], nkey[R];
-    if (cb >= ce) continue;  // (chunks of a node are never empty; the clamps below need a key)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = cb + w * PW + r * 64 + l;
-      nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
-    }
-    for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
-      const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
-#pragma unroll
-      for (int r = 0; r < R; ++r) key[r] = nkey[r];
-      const uint32_t t1 = t0 + TS;
+    // (chunks of a node are never empty; the clamped addresses below need a
+    // key: an empty chunk skips the tiles and leaves neutral ranges)
+    if (cb < ce) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
+        const uint32_t i = cb + w * PW + r * 64 + l;
         nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
       }
-      // A: bucket of every key (all table reads issued before any atomic),
-      // rank inside the tile's bucket, child ranges
-      uint32_t qq[R];
+      for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
+        const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+        for (int r = 0; r < R; ++r) key[r] = nkey[r];
+        const uint32_t t1 = t0 + TS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
-        bad |= q >= nb;  // range check: cannot happen for a consistent model
-        qq[r] = q < nb ? q : nb - 1;
-      }
-      uint32_t code[R];
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
+          nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
+        }
+        // A: bucket of every key (all table reads issued before any atomic),
+        // rank inside the tile's bucket, child ranges
+        uint32_t qq[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        const bool valid = i < tn;
-        const uint32_t q = qq[r];
-        const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
-        const uint64_t act = __ballot(valid);
-        uint32_t rk = 0;
-        if (act == ~0ull && __all(q == q0)) {
-          // the whole wave in one bucket (runs of near-equal keys)
-          uint32_t b0 = 0;
-          if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
-          rk = __builtin_amdgcn_readfirstlane(b0) + l;
-          if (any_glb && cmapf[q0]) {
-            const uint64_t im = img_of<KT>(key[r]);
-            const uint64_t wlo = wave_min_u64(im), whi = wave_max_u64(im);
-            if (l == 0) {
-              atomicMin(&mmlo[q0], (unsigned long long)wlo);
-              atomicMax(&mmhi[q0], (unsigned long long)whi);
+        for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
+          bad |= q >= nb;  // range check: cannot happen for a consistent model
+          qq[r] = q < nb ? q : nb - 1;
+        }
+        uint32_t code[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          const bool valid = i < tn;
+          const uint32_t q = qq[r];
+          const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
+          const uint64_t act = __ballot(valid);
+          uint32_t rk = 0;
+          if (act == ~0ull && __all(q == q0)) {
+            // the whole wave in one bucket (runs of near-equal keys)
+            uint32_t b0 = 0;
+            if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
+            rk = __builtin_amdgcn_readfirstlane(b0) + l;
+            if (any_glb && cmapf[q0]) {
+              const uint64_t im = img_of<KT>(key[r]);
+              const uint64_t wlo = wave_min_u64(im), whi = wave_max_u64(im);
+              if (l == 0) {
+                atomicMin(&mmlo[q0], (unsigned long long)wlo);
+                atomicMax(&mmhi[q0], (unsigned long long)whi);
+              }
+            }
+          } else if (valid) {
+            rk = atomicAdd(&tcnt[q], 1u);
+            if (any_glb && cmapf[q]) {
+              const unsigned long long im = img_of<KT>(key[r]);
+              atomicMin(&mmlo[q], im);
+              atomicMax(&mmhi[q], im);
             }
           }
-        } else if (valid) {
-          rk = atomicAdd(&tcnt[q], 1u);
-          if (any_glb && cmapf[q]) {
-            const unsigned long long im = img_of<KT>(key[r]);
-            atomicMin(&mmlo[q], im);
-            atomicMax(&mmhi[q], im);
+          code[r] = (q << 16) | rk;
+        }
+        __syncthreads();
+        // B (wave 0): tile bucket starts, write bases, next run offsets, counters
+        if (w == 0) {
+          uint32_t carry = 0;
+          for (uint32_t q0 = 0; q0 < nb; q0 += 64) {
+            const uint32_t q = q0 + l;
+            const uint32_t v = q < nb ? tcnt[q] : 0u;
+            const uint32_t x = wave_incl_scan(v);
+            if (q < nb) {
+              const uint32_t st = carry + x - v;
+              const uint32_t ro = runoff[q];
+              tstart[q] = st;
+              wbase[q] = ro - st;
+              runoff[q] = ro + v;
+              tcnt[q] = 0u;
+            }
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
           }
         }
-        code[r] = (q << 16) | rk;
-      }
-      __syncthreads();
-      // B (wave 0): tile bucket starts, write bases, next run offsets, counters
-      if (w == 0) {
-        uint32_t carry = 0;
-        for (uint32_t q0 = 0; q0 < nb; q0 += 64) {
-          const uint32_t q = q0 + l;
-          const uint32_t v = q < nb ? tcnt[q] : 0u;
-          const uint32_t x = wave_incl_scan(v);
-          if (q < nb) {
-            const uint32_t st = carry + x - v;
-            const uint32_t ro = runoff[q];
-            tstart[q] = st;
-            wbase[q] = ro - st;
-            runoff[q] = ro + v;
-            tcnt[q] = 0u;
-          }
-          carry += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-        }
-      }
-      __syncthreads();
-      // C: stage keys in bucket order
+        __syncthreads();
+        // C: stage keys in bucket order
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t i = w * PW + r * 64 + l;
-        if (i < tn) {
-          const uint32_t q = code[r] >> 16;
-          const uint32_t pos = tstart[q] + (code[r] & 0xffffu);
-          if (pos < (uint32_t)TS) {
-            sk[pos] = key[r];
-            sb[pos] = (uint16_t)q;
-          } else {
-            bad = true;
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          if (i < tn) {
+            const uint32_t q = code[r] >> 16;
+            const uint32_t pos = tstart[q] + (code[r] & 0xffffu);
+            if (pos < (uint32_t)TS) {
+              sk[pos] = key[r];
+              sb[pos] = (uint16_t)q;
+            } else {
+              bad = true;
+            }
           }
         }
-      }
-      __syncthreads();
-      // D: write runs (consecutive staged keys of one bucket go to consecutive
-      // addresses); no barrier after it: the next tile's rank phase touches
-      // only tcnt and the min/max, and its bucket-start phase comes after the
-      // next barrier
-      // (per half: the staged ids, then their write bases, then the keys,
-      // each a batch of independent LDS reads).  A lane past the tile's end
-      // repeats the store of the tile's last key: same value, same address.
-      {
-        constexpr int H = R / 2 > 0 ? R / 2 : 1;
+        __syncthreads();
+        // D: write runs (consecutive staged keys of one bucket go to consecutive
+        // addresses); no barrier after it: the next tile's rank phase touches
+        // only tcnt and the min/max, and its bucket-start phase comes after the
+        // next barrier
+        // (per half: the staged ids, then their write bases, then the keys,
+        // each a batch of independent LDS reads).  A lane past the tile's end
+        // repeats the store of the tile's last key: same value, same address.
+        {
+          constexpr int H = R / 2 > 0 ? R / 2 : 1;
 #pragma unroll
-        for (int h = 0; h < R; h += H) {
-          uint32_t qd[H], wb[H], ic[H];
-          uint64_t kd[H];
+          for (int h = 0; h < R; h += H) {
+            uint32_t qd[H], wb[H], ic[H];
+            uint64_t kd[H];
 #pragma unroll
-          for (int r = 0; r < H; ++r) {
-            const uint32_t i = (h + r) * NT + threadIdx.x;
-            ic[r] = i < tn ? i : tn - 1;
-            qd[r] = sb[ic[r]];
-          }
+            for (int r = 0; r < H; ++r) {
+              const uint32_t i = (h + r) * NT + threadIdx.x;
+              ic[r] = i < tn ? i : tn - 1;
+              qd[r] = sb[ic[r]];
+            }
 #pragma unroll
-          for (int r = 0; r < H; ++r) wb[r] = wbase[qd[r]];
+            for (int r = 0; r < H; ++r) wb[r] = wbase[qd[r]];
 #pragma unroll
-          for (int r = 0; r < H; ++r) kd[r] = sk[ic[r]];
+            for (int r = 0; r < H; ++r) kd[r] = sk[ic[r]];
 #pragma unroll
-          for (int r = 0; r < H; ++r) {
-            const uint32_t rel = wb[r] + ic[r];
-            bad |= rel >= nd.len;
-            gst(dk)[nd.off + (rel < nd.len ? rel : nd.len - 1)] = kd[r];
+            for (int r = 0; r < H; ++r) {
+              const uint32_t rel = wb[r] + ic[r];
+              bad |= rel >= nd.len;
+              gst(dk)[nd.off + (rel < nd.len ? rel : nd.len - 1)] = kd[r];
+            }
           }
         }
       }

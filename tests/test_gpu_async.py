@@ -74,12 +74,17 @@ def test_extra_levels_take_a_second_finish_pass(P, oracle):
 
 
 def test_deferred_profile_equals_waiting_profile(P):
+    # argsort: its scatters are stable, so every call builds the same
+    # recursion and the figures of the two modes must agree exactly (keys
+    # alone may sit in any order inside a bucket, so the samples of deeper
+    # levels, and the arrays they produce, can differ from call to call)
     import torch
     n = 2_000_000
     banner(f"profile of enqueue-only calls, n={n}")
     d = to_dev(datagen.f64("normal", n, 2))
-    out = torch.empty_like(d)
-    ws = P.workspace(P.KEY_F64, n)
+    ko = torch.empty_like(d)
+    io = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = P.workspace(P.KEY_F64, n, with_payload=True)
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     P.pcf_profile_select(None)
     P.pcf_profile_enable(True)
@@ -87,7 +92,7 @@ def test_deferred_profile_equals_waiting_profile(P):
     for status in (None, st):
         P.pcf_profile_read(reset=True)
         for _ in range(3):
-            P.pcf_sort_f64(d, out=out, ws=ws, d_status=status)
+            P.pcf_argsort(d, keys_out=ko, idx_out=io, ws=ws, d_status=status)
         torch.cuda.synchronize()
         figs.append(P.pcf_profile_read(reset=True))
     P.pcf_profile_enable(False)
