@@ -1218,6 +1218,10 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
     // failures are collected and reported after the unit.
     bool bad = false;
     uint64_t key[R], nkey[R];
+    // the common case: a PCF node with a byte table and an unhalved range,
+    // whose bucket needs none of the general Bucketer's per-key tests (same
+    // arithmetic, same result)
+    const bool fast = KT == KT_F64 && nd.kind == NK_PCF && tab8 && !bk.f.halves;
     // (chunks of a node are never empty; the clamped addresses below need a
     // key: an empty chunk skips the tiles and leaves neutral ranges)
     if (cb < ce) {
@@ -1239,14 +1243,31 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
         // A: bucket of every key (all table reads issued before any atomic),
         // rank inside the tile's bucket, child ranges
         uint32_t qq[R];
+        if (fast) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+          for (int r = 0; r < R; ++r) {
+            const double pos = KT == KT_F64
+                                   ? (__longlong_as_double((long long)key[r]) - bk.f.lo) * bk.f.s
+                                   : (double)(key[r] - bk.f.lo_bits) * bk.f.s;
+            const uint32_t k = (uint32_t)floor(pos);
+            qq[r] = k < bk.f.beta ? k : bk.f.beta;
+          }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const uint32_t i = w * PW + r * 64 + l;
-          uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
-          bad |= q >= nb;  // range check: cannot happen for a consistent model
-          qq[r] = q < nb ? q : nb - 1;
+          for (int r = 0; r < R; ++r) {
+            const uint32_t i = w * PW + r * 64 + l;
+            const uint32_t q = tab[qq[r]];  // T_i <= gamma < nb
+            qq[r] = i < tn ? q : 0u;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const uint32_t i = w * PW + r * 64 + l;
+            uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
+            bad |= q >= nb;  // range check: cannot happen for a consistent model
+            qq[r] = q < nb ? q : nb - 1;
+          }
         }
         uint32_t code[R];
 #pragma unroll
