@@ -1681,13 +1681,27 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
     if (fast) {
       // first level from registers: bin, rank inside the bin
       uint32_t bp[EPT];
+      if (KT == KT_F64 && !f.halves) {
+        // an unhalved fp64 range: the bin without bin_of's per-key select
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        const uint32_t i = threadIdx.x + k * NT;
-        if (i < m) {
-          uint32_t b = bin_of<KT>(f, bits_of_img<KT>(kk[k]));
-          b = b < m - 1 ? b : m - 1;
-          bp[k] = b | (atomicAdd(&sm.cnt[b], 1u) << 16);
+        for (int k = 0; k < EPT; ++k) {
+          const uint32_t i = threadIdx.x + k * NT;
+          if (i < m) {
+            const double v = __longlong_as_double((long long)bits_of_img<KT>(kk[k]));
+            const uint32_t b0 = (uint32_t)floor((v - f.lo) * f.s);
+            const uint32_t b = b0 < m - 1 ? b0 : m - 1;
+            bp[k] = b | (atomicAdd(&sm.cnt[b], 1u) << 16);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const uint32_t i = threadIdx.x + k * NT;
+          if (i < m) {
+            uint32_t b = bin_of<KT>(f, bits_of_img<KT>(kk[k]));
+            b = b < m - 1 ? b : m - 1;
+            bp[k] = b | (atomicAdd(&sm.cnt[b], 1u) << 16);
+          }
         }
       }
       __syncthreads();
