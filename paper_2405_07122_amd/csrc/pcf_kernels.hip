@@ -1791,14 +1791,62 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
         k5_level<KT, CAP, NT, PAY>(sm, rs, re, rdepth, rlo, rhi, tau);
       }
     }
-    // counting rank inside final segments, then the write-out.  With a
-    // payload, all reads (LDS keys and the payload, which may live in the very
-    // range being written) happen before a barrier and all writes after it.
-    // Keys alone in their segment (the common case) take their place at once;
-    // the others are ranked in a second, non-unrolled pass.  With a payload,
-    // ranks and payload words are staged in LDS (seg and cnt are free by
-    // now) and written after a barrier: the payload may live in the very
-    // range being written.
+    if (!PAY) {
+      // final ranks inside the segments: a key alone in its segment already
+      // sits at its rank; the others count the keys of their segment that
+      // precede them (ties by position).  All LDS reads of this pass come
+      // before a barrier; then the keys that are not in place move to their
+      // ranks in LDS, and after a second barrier the item leaves in coalesced
+      // rows, with nontemporal stores: nothing reads the output again here,
+      // and lines left dirty in L2 slowed the next sort's first scatter.  The
+      // next item writes keys only after its first barrier.
+      uint64_t kv[EPT];
+      uint32_t rk[EPT];
+#pragma unroll
+      for (int kq = 0; kq < EPT; ++kq) {
+        const uint32_t i = threadIdx.x + kq * NT;
+        rk[kq] = i;
+        if (i < m) {
+          const uint32_t sg = sm.seg[i];
+          const uint32_t a = sg & 0xffffu, b = sg >> 16;
+          const uint64_t k = sm.key[i];
+          uint32_t rnk = a;
+          if (b - a > 1) {
+            for (uint32_t q = a; q < b; ++q) {
+              const uint64_t kq2 = sm.key[q];
+              rnk += (kq2 < k) || (kq2 == k && q < i);
+            }
+          }
+          kv[kq] = k;
+          rk[kq] = rnk;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < EPT; ++kq) {
+        const uint32_t i = threadIdx.x + kq * NT;
+        if (i < m && rk[kq] != i) {
+          if (rk[kq] < m) sm.key[rk[kq]] = kv[kq];
+          else flag_internal(c);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < EPT; ++kq) {
+        const uint32_t i = threadIdx.x + kq * NT;
+        if (i < m) __builtin_nontemporal_store(bits_of_img<KT>(sm.key[i]), ok + i);
+      }
+      continue;
+    }
+    // with a payload: counting rank inside final segments, then the
+    // write-out.  All reads (LDS keys and the payload, which may live in the
+    // very range being written) happen before a barrier and all writes after
+    // it: ranks and payload words are staged in LDS at each key's own
+    // position (seg and cnt are free by now).  Keys in segments of several
+    // keys are ranked in a second, non-unrolled pass.  Outputs are written
+    // with nontemporal stores, as for keys alone.  (Moving keys and payload
+    // words to their ranks in LDS for a coalesced write-out, as for keys
+    // alone, holds registers across a barrier and spilled here.)
     uint32_t multi = 0;  // bit kq: the key sits in a segment of several keys
 #pragma unroll
     for (int kq = 0; kq < EPT; ++kq) {
@@ -1808,12 +1856,10 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
         const uint32_t a = sg & 0xffffu, b = sg >> 16;
         if (b - a > 1) {
           multi |= 1u << kq;
-        } else if (PAY) {
+        } else {
           const uint32_t ps = sm.pos[i];
           sm.cnt[i] = it.vsrc ? gld(it.vsrc)[ps] : (uint32_t)it.rel + ps;
           sm.seg[i] = a;
-        } else {
-          ok[a] = bits_of_img<KT>(sm.key[i]);
         }
       }
     }
@@ -1824,38 +1870,30 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
       const uint32_t sg = sm.seg[i];
       const uint32_t a = sg & 0xffffu, b = sg >> 16;
       const uint64_t k = sm.key[i];
-      const uint32_t ps = PAY ? (uint32_t)sm.pos[i] : i;
+      const uint32_t ps = sm.pos[i];
       uint32_t rnk = a;
       for (uint32_t q = a; q < b; ++q) {
         const uint64_t kq2 = sm.key[q];
-        const uint32_t pq = PAY ? (uint32_t)sm.pos[q] : q;
+        const uint32_t pq = sm.pos[q];
         rnk += (kq2 < k) || (kq2 == k && pq < ps);
       }
-      if (PAY) {
-        // a thread reads seg only at its own positions: the rank can take
-        // their place
-        sm.cnt[i] = it.vsrc ? gld(it.vsrc)[ps] : (uint32_t)it.rel + ps;
-        sm.seg[i] = rnk;
-      } else if (rnk < m) {
-        ok[rnk] = bits_of_img<KT>(k);
-      } else {
-        flag_internal(c);
-      }
+      // a thread reads seg only at its own positions: the rank can take
+      // their place
+      sm.cnt[i] = it.vsrc ? gld(it.vsrc)[ps] : (uint32_t)it.rel + ps;
+      sm.seg[i] = rnk;
     }
-    if (PAY) {
-      __syncthreads();
+    __syncthreads();
 #pragma unroll
-      for (int kq = 0; kq < EPT; ++kq) {
-        const uint32_t i = threadIdx.x + kq * NT;
-        if (i < m) {
-          const uint32_t rnk = sm.seg[i];
-          if (rnk >= m) {
-            flag_internal(c);
-            continue;
-          }
-          ok[rnk] = bits_of_img<KT>(sm.key[i]);
-          p.out_vals[it.off + rnk] = sm.cnt[i];
+    for (int kq = 0; kq < EPT; ++kq) {
+      const uint32_t i = threadIdx.x + kq * NT;
+      if (i < m) {
+        const uint32_t rnk = sm.seg[i];
+        if (rnk >= m) {
+          flag_internal(c);
+          continue;
         }
+        __builtin_nontemporal_store(bits_of_img<KT>(sm.key[i]), ok + rnk);
+        __builtin_nontemporal_store(sm.cnt[i], p.out_vals + it.off + rnk);
       }
     }
     __syncthreads();
