@@ -416,8 +416,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
-              f"is described in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a path over several "
+              f"GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

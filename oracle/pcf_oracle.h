@@ -20,7 +20,7 @@
  *   - The parameter rule of the PCF theorems (Sec. 3.3):
  *     alpha = beta = gamma = delta = floor(n^{3/4}); tau = 100 as in Sec. 4.1.
  *
- * Readings where the paper is silent (each one is listed in the design doc):
+ * Readings where the paper is silent:
  *   - sampling is with replacement, index j of a node drawn from SplitMix64
  *     (counter-based: the j-th output of SplitMix64 started at the node seed),
  *     reduced to [0, n) by the high 64 bits of the 128-bit product;
