@@ -1596,13 +1596,16 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
       pre[k] = i < it0.len ? __builtin_nontemporal_load(gld(s0) + i) : 0ull;
     }
   }
-  // the next item's descriptor is loaded while this one is sorted (its
-  // latency otherwise starts every item: 10 % of the small class's time)
+  // fp64 keys: the next item's descriptor is loaded while this one is
+  // sorted (its latency otherwise starts every item: 10 % of the small
+  // class's time).  The uint64 instantiations keep the plain load: holding
+  // the descriptor there raised their register spills and slowed them.
+  constexpr bool IPF = KT == KT_F64;
   Item nit = {};
-  if (first + blockIdx.x < total) nit = p.items[cls][first + blockIdx.x];
+  if (IPF && first + blockIdx.x < total) nit = p.items[cls][first + blockIdx.x];
   for (uint32_t ii = first + blockIdx.x; ii < total; ii += gridDim.x) {
-    const Item it = nit;
-    if (ii + gridDim.x < total) nit = p.items[cls][ii + gridDim.x];
+    const Item it = IPF ? nit : p.items[cls][ii];
+    if (IPF && ii + gridDim.x < total) nit = p.items[cls][ii + gridDim.x];
     const uint32_t m = it.len;
     done_keys += m;
     uint64_t kk[EPT];
