@@ -460,22 +460,33 @@ def main():
 
     # timed region: events around the graded scatter launches only (events
     # around every launch would add a gap after each of them).  Each call
-    # reports its data status to a device word (the asynchronous form of the
-    # call), checked after the region, so no call waits for the one before.
+    # waits for its outcome (the host reads the level counts once after the
+    # planned levels, while the LDS finish already runs, and at the end).
     pcfsort.pcf_profile_select(["scatter"])
     pcfsort.pcf_profile_enable(True)
     pcfsort.pcf_profile_read(reset=True)
-    status = torch.zeros(1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws, d_status=status)
+        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = pcfsort.pcf_profile_read(reset=True)
-    if int(status.item()) != 0:
-        log(f"a timed sort reported status {int(status.item())}")
+    pcfsort.pcf_profile_enable(False)
+
+    # the enqueue-only form of the same calls: a status word per step, the
+    # fixed chain of levels (no host read), checked after the region
+    status = torch.zeros(args.steps, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    for k in range(args.steps):
+        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws, d_status=status[k:k + 1])
+    torch.cuda.synchronize()
+    enqueue_ms = (time.perf_counter() - te) / args.steps * 1e3
+    if bool((status != 0).any()):
+        log(f"a timed sort reported status {status.cpu().tolist()}")
         sys.exit(1)
+    pcfsort.pcf_profile_enable(True)
     # per-kernel breakdown: one more sort per array, outside the timed region
     pcfsort.pcf_profile_select(None)
     for d in dists:
@@ -571,6 +582,8 @@ def main():
                      "traffic": traffic, "bytes_per_key": SCATTER_BYTES_KEYS,
                      "avg_launch_ms": avg_ms, "launches": sc["launches"]},
         "cpu_baseline": cpu,
+        "enqueue_only": {"ms_per_sort": enqueue_ms,
+                         "form": "status word given: fixed chain of levels, returns after enqueue"},
         "kernels": kernels,
         **extra,
     }

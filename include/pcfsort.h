@@ -18,9 +18,16 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *   - Calls return a pcf_status.  Argument errors are reported synchronously
  *     and nothing is enqueued.  The sort calls enqueue their kernels on
- *     `stream`; between recursion levels they may wait for `stream` to read
- *     back a few bytes of work counts, so they can block.  On return every
- *     kernel is enqueued; the output is complete once `stream` is synchronized.
+ *     `stream`.  Given a device status word (d_status != NULL), a call
+ *     enqueues a fixed chain of recursion levels (enough for any input of n
+ *     keys: the delta rule's levels plus 9 radix levels; empty levels exit at
+ *     once), the LDS finish and a kernel that writes the status word, and
+ *     returns without waiting: with a caller workspace such a call can be
+ *     captured into a hipGraph.  Without a status word a call waits for
+ *     `stream`: it reads back a few bytes of level counts after the planned
+ *     levels (runs only the extra levels an input needs) and at the end, and
+ *     returns the data status.  The output is complete once `stream` is
+ *     synchronized.
  *   - Keys are totally ordered by value.  fp64 keys must be finite and must
  *     not be -0.0 (then the ascending order is unique bit for bit); a key that
  *     breaks this makes the call return PCF_ERR_INVALID_KEY (detected on the
@@ -105,6 +112,9 @@ int pcf_argsort(int key_type, const void *d_keys_in, void *d_keys_out, uint32_t 
  * payload every segment must be shorter than 2^32).  d_offsets: device array
  * of num_segments + 1 non-decreasing uint64 CSR offsets, d_offsets[0] = 0;
  * empty segments are allowed.  total_keys = d_offsets[num_segments] < 2^32.
+ * Offsets that break these rules are found on the device: the call's data
+ * status is then PCF_ERR_INVALID_ARGUMENT (status word or return value) and
+ * the output is unspecified; no kernel accesses memory outside the buffers.
  * With a caller workspace (d_ws != NULL) the batch runs as one fixed launch
  * chain (enough levels for any input of total_keys keys, empty levels exit at
  * once) that is captured into a hipGraph on the first call with a given
@@ -295,11 +305,21 @@ typedef struct {
 } pcf_serve_stats;
 
 int pcf_serve_create(const pcf_serve_config *cfg, pcf_server **out);
-/* Never blocks.  d_keys (n keys of key_type) must stay valid and unchanged
- * until the request is done.  A request that alone exceeds the budget returns
- * PCF_ERR_OUT_OF_MEMORY. */
+/* Never blocks.  d_keys (n keys of key_type) must already hold their final
+ * contents (any device work that writes them has completed), and must stay
+ * valid and unchanged until the request is done: the server's own streams
+ * read them, in no order with the caller's streams.  Keys written by work
+ * still in flight on a stream: use pcf_serve_submit_after.  A request that
+ * alone exceeds the budget returns PCF_ERR_OUT_OF_MEMORY. */
 int pcf_serve_submit(pcf_server *s, int key_type, const void *d_keys, size_t n, int want_argsort,
                      uint64_t *ticket);
+/* As pcf_serve_submit, for keys that work still in flight writes: the batch
+ * that sorts the request first makes its stream wait for ready_event (a
+ * hipEvent_t, passed as void*, recorded by the caller after that work; NULL =
+ * ready now).  The event must not be destroyed until the request is done;
+ * recording it again in the meantime can only delay the batch. */
+int pcf_serve_submit_after(pcf_server *s, int key_type, const void *d_keys, size_t n,
+                           int want_argsort, void *ready_event, uint64_t *ticket);
 /* Non-blocking: PCF_OK and *out filled when done, PCF_PENDING otherwise. */
 int pcf_serve_poll(pcf_server *s, uint64_t ticket, pcf_result *out);
 /* Blocks until the request is done (or timeout_ms passes: PCF_PENDING). */

@@ -133,7 +133,11 @@ static double FN(pos)(const FN(binfn) *f, KEY v)
     double off;
 #if IS_F64
     if (f->halves)
+#ifdef PCFO_PLANT_HALF_OFFSET
+        off = v * 0.5 - f->lo; /* planted mistake: only the key is halved */
+#else
         off = v * 0.5 - f->lo * 0.5;
+#endif
     else
         off = v - f->lo;
 #else

@@ -29,9 +29,9 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _compile(src: str, build_dir: str = BUILD_DIR, defines: tuple = ()) -> str:
+def _compile(src: str, build_dir: str = BUILD_DIR) -> str:
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    flags = [*COMMON, *[f"-D{d}" for d in defines]]
+    flags = list(COMMON)
     cmd = [HIPCC, *flags, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "hip", *flags, "-c", src, "-o", obj]
@@ -42,13 +42,12 @@ def _compile(src: str, build_dir: str = BUILD_DIR, defines: tuple = ()) -> str:
     return obj
 
 
-def build(verbose: bool = False, out: str = LIB, defines: tuple = (),
-          build_dir: str = BUILD_DIR) -> str:
-    """Compiles and links the library; `defines` select compile-time variants."""
+def build(verbose: bool = False, out: str = LIB, build_dir: str = BUILD_DIR) -> str:
+    """Compiles and links the library."""
     os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda f: _compile(f, build_dir, tuple(defines)), srcs))
+        objs = list(ex.map(lambda f: _compile(f, build_dir), srcs))
     tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -210,7 +210,8 @@ struct LevelCtr {
 };
 
 struct Ctl {
-  int32_t status;      // 0 or the data error (PCF_ERR_INVALID_KEY)
+  int32_t status;      // 0 or the data error (PCF_ERR_INVALID_KEY, or PCF_ERR_INVALID_ARGUMENT
+                       // for CSR offsets that are not a partition of [0, n))
   uint32_t overflow;   // a capacity bound was exceeded (library bug guard); kernels
                        // read status and overflow together as one 64-bit word
   uint32_t item_count[3];
@@ -256,7 +257,11 @@ struct Plan {
   uint32_t* task_node[2];
   MinMax* mmr;          // per-unit ranges of the roots (range kernel)
   uint64_t* sbuf0;      // sample keys of a single root, gathered by the range kernel (or null)
-  uint32_t sbuf0_cap, pad0;
+  uint32_t sbuf0_cap;
+  // global levels this call may run (levels 0 .. nlev - 1): a radix node
+  // takes log-scale digits only while the levels left can still finish its
+  // children with linear digits
+  uint32_t nlev;
   uint32_t cap_nodes, cap_units, cap_aux, pad;
   unsigned long long cap_table, cap_cm;
   Item* items[3];
@@ -265,7 +270,6 @@ struct Plan {
   uint32_t* trace_b;
   PolicyDev pol;
   uint64_t seed;
-  uint64_t n_total;  // keys in the whole call (bound of every output position)
 };
 
 // Parameters of a node of `len` keys (gamma + 1 = nb buckets, beta bins,

@@ -19,22 +19,6 @@
 #include "pcf_driver.h"
 #include "pcf_kernels.h"
 
-// Compile-time variants (defaults: the measured best on MI355X):
-//   PCF_KEYS_SCATTER 0: keys-only levels use the generic scatter kernel;
-//                    1: the three-barrier keys-only kernel, 4096-key tiles,
-//                       512 threads, two workgroups per CU;
-//                    2: the same with 8192-key tiles, 1024 threads, one
-//                       workgroup per CU (default: the same scatter time with
-//                       half the bucket-edge lines, and count and fit gain
-//                       from the longer work units: 2 % faster per sort).
-//   PCF_K5_CLASSES   2: LDS-finish classes <= 2048 and <= 8192 keys; 3: adds <= 4096.
-#ifndef PCF_KEYS_SCATTER
-#define PCF_KEYS_SCATTER 2
-#endif
-#ifndef PCF_K5_CLASSES
-#define PCF_K5_CLASSES 3
-#endif
-
 namespace pcf {
 
 static thread_local int g_last_hip_error = 0;
@@ -238,8 +222,8 @@ static thread_local CallProf t_prof;
 
 // LDS-finish classes (LDS capacity and workgroup size).
 constexpr int K5_SMALL_CAP = 2048, K5_SMALL_NT = 256;
-constexpr int K5_MID_CAP = 4096, K5_MID_NT = PCF_K5_MID_NT;
-constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = PCF_K5_BIG_NT;
+constexpr int K5_MID_CAP = 4096, K5_MID_NT = 512;
+constexpr int K5_BIG_CAP = 8192, K5_BIG_NT = 1024;
 // Scatter workgroup and tile: keys only (unstable ranks) / with a payload (stable).
 constexpr int SC_NT = 512, SC_TS_KEYS = 8192, SC_TS_PAY = 2048;
 
@@ -369,11 +353,13 @@ static int ctl_readback_slot(Ctl** pin, hipEvent_t* ev) {
 // level holds nodes (failed buckets of skewed inputs) do more levels follow,
 // each with a host read, and a second finish pass for their items.
 // fixed_levels > 0: exactly that many levels are launched with no host
-// synchronization (empty levels exit at once), so the launches can be
-// captured into a graph.
+// synchronization (empty levels exit at once), then one finish pass; with
+// `capture` the function returns right there (the launches are being
+// captured into a graph), otherwise it ends like any call: deferred profile
+// marks with a status word, a wait for the outcome without one.
 template <int KT, int PAY>
 static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
-                     int fixed_levels) {
+                     int fixed_levels, bool capture) {
   hipStream_t st = a.stream;
   const int cus = device_cus();
   if (cus <= 0) return PCF_ERR_UNSUPPORTED;
@@ -404,7 +390,6 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   p.mmr = reinterpret_cast<MinMax*>(ws + lay.mmr);
   p.sbuf0 = (a.nseg == 1 && !a.trace) ? reinterpret_cast<uint64_t*>(ws + lay.sbuf0) : nullptr;
   p.sbuf0_cap = pol.max_samples;
-  p.pad0 = 0;
   p.cap_nodes = lay.cap_nodes;
   p.cap_units = lay.cap_units;
   p.cap_aux = lay.cap_aux;
@@ -424,9 +409,11 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
       sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY, (int)pol.model).total;
     }
   } else {
-    sc_ts = PCF_KEYS_SCATTER == 2 ? 8192 : 4096;
-    sc_lds = PCF_KEYS_SCATTER == 0 ? scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, 4096, 0, (int)pol.model).total
-                                   : scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
+    // 8192-key tiles, 1024 threads, one workgroup per CU: the same scatter
+    // time as two 512-thread workgroups with 4096-key tiles, half the
+    // bucket-edge lines, and longer work units for the count and fit
+    sc_ts = 8192;
+    sc_lds = scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
     if (sc_lds > 160 * 1024 - 1024) {
       sc_ts = 4096;
       sc_lds = scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
@@ -455,14 +442,14 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   pd.tau = pol.tau;
   pd.model = pol.model;
   pd.small_cap = K5_SMALL_CAP;
-  pd.mid_cap = PCF_K5_CLASSES == 2 ? K5_SMALL_CAP : K5_MID_CAP;
+  pd.mid_cap = K5_MID_CAP;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
     pd.prof = g_prof_on ? 1u : 0u;
   }
   p.pol = pd;
   p.seed = (uint64_t)pol.seed;
-  p.n_total = a.n;
+  p.nlev = fixed_levels > 0 ? (uint32_t)fixed_levels : (a.trace ? 1u : (uint32_t)(MAX_LEVELS - 1));
 
   RootArgs ra = {};
   ra.keys = a.keys_in;
@@ -532,9 +519,6 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
         else
           hipLaunchKernelGGL((k_scatter<KT, SC_NT, SC_TS_PAY / 2, 1>), dim3(g_sc), dim3(SC_NT),
                              sl.total, st, p, L, io, bins_lds, lay.nbmax);
-      } else if (PCF_KEYS_SCATTER == 0) {
-        hipLaunchKernelGGL((k_scatter<KT, SC_NT, 4096, 0>), dim3(g_sc), dim3(SC_NT), sl.total, st,
-                           p, L, io, bins_lds, lay.nbmax);
       } else {
         if (sc_ts == 8192)
           hipLaunchKernelGGL((k_scatter_keys<KT, 2 * SC_NT, 8192>), dim3(g_sc), dim3(2 * SC_NT),
@@ -583,13 +567,6 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     return PCF_OK;
   };
   int r = PCF_OK;
-  if (fixed_levels > 0) {
-    // a fixed chain (graph capture): every level, one finish pass, no host reads
-    for (int L = 0; L < fixed_levels; ++L)
-      if ((r = level(L)) != PCF_OK) return r;
-    if (a.levels_run) *a.levels_run = (uint32_t)levels;
-    return finish(fixed_levels);
-  }
   if (a.trace) {
     // one level with the caller's parameters, then its model and partition
     if ((r = level(0)) != PCF_OK) return r;
@@ -629,36 +606,44 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     }
     return PCF_OK;
   }
-  // the planned levels run without host reads; the control block is then
-  // copied back while the LDS finish of the items so far already runs, so
-  // the device does not wait for the host's decision on further levels
-  for (int L = 0; L < planned; ++L)
-    if ((r = level(L)) != PCF_OK) return r;
-  Ctl* pin = nullptr;
-  hipEvent_t ev = nullptr;
-  if ((r = ctl_readback_slot(&pin, &ev)) != PCF_OK) return r;
-  PCF_HIP(hipMemcpyAsync(pin, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-  PCF_HIP(hipEventRecord(ev, st));
-  if ((r = finish(-1)) != PCF_OK) return r;
-  PCF_HIP(hipEventSynchronize(ev));
-  std::memcpy(&hc, pin, sizeof(Ctl));
-  if (hc.status) return hc.status;
-  if (hc.overflow) return overflow_status(hc.overflow);
-  if (hc.lv[planned].num_nodes != 0) {
-    // rare (failed buckets of skewed inputs): more levels, one host read each
-    for (int L = planned;; ++L) {
-      if (L >= MAX_LEVELS - 1) return PCF_ERR_OUT_OF_MEMORY;
+  if (fixed_levels > 0) {
+    // a fixed chain: every level, one finish pass, no host reads
+    for (int L = 0; L < fixed_levels; ++L)
       if ((r = level(L)) != PCF_OK) return r;
-      if ((r = readback()) != PCF_OK) return r;
-      if (hc.status) return hc.status;
-      if (hc.overflow) return overflow_status(hc.overflow);
-      if (hc.lv[L + 1].num_nodes == 0) break;
-    }
+    if (a.levels_run) *a.levels_run = (uint32_t)levels;
+    if ((r = finish(fixed_levels)) != PCF_OK) return r;
+    if (capture) return PCF_OK;
+  } else {
+    // the planned levels run without host reads; the control block is then
+    // copied back while the LDS finish of the items so far already runs, so
+    // the device does not wait for the host's decision on further levels
+    for (int L = 0; L < planned; ++L)
+      if ((r = level(L)) != PCF_OK) return r;
+    Ctl* pin = nullptr;
+    hipEvent_t ev = nullptr;
+    if ((r = ctl_readback_slot(&pin, &ev)) != PCF_OK) return r;
+    PCF_HIP(hipMemcpyAsync(pin, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    PCF_HIP(hipEventRecord(ev, st));
     if ((r = finish(-1)) != PCF_OK) return r;
+    PCF_HIP(hipEventSynchronize(ev));
+    std::memcpy(&hc, pin, sizeof(Ctl));
+    if (hc.status) return hc.status;
+    if (hc.overflow) return overflow_status(hc.overflow);
+    if (hc.lv[planned].num_nodes != 0) {
+      // rare (failed buckets of skewed inputs): more levels, one host read each
+      for (int L = planned;; ++L) {
+        if (L >= MAX_LEVELS - 1) return PCF_ERR_OUT_OF_MEMORY;
+        if ((r = level(L)) != PCF_OK) return r;
+        if ((r = readback()) != PCF_OK) return r;
+        if (hc.status) return hc.status;
+        if (hc.overflow) return overflow_status(hc.overflow);
+        if (hc.lv[L + 1].num_nodes == 0) break;
+      }
+      if ((r = finish(-1)) != PCF_OK) return r;
+    }
+    if (a.levels_run) *a.levels_run = (uint32_t)levels;
   }
-  if (a.levels_run) *a.levels_run = (uint32_t)levels;
   PCF_HIP(hipGetLastError());
-  if (fixed_levels > 0) return PCF_OK;
   if (a.d_status) return t_prof.defer(p.ctl, a.n);  // errors reach the status word
   PCF_HIP(hipMemcpyAsync(&hc, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   PCF_HIP(hipStreamSynchronize(st));
@@ -709,9 +694,6 @@ static int set_attrs_typed() {
     if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter_keys<KT, 2 * SC_NT, 8192>), sc_max)) !=
         PCF_OK)
       return r;
-    if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter<KT, SC_NT, 4096, 0>), sc_max)) !=
-        PCF_OK)
-      return r;
     if ((r = allow_lds(reinterpret_cast<const void*>(&k_scatter_keys<KT, SC_NT, 4096>), sc_max)) !=
         PCF_OK)
       return r;
@@ -732,12 +714,12 @@ static int set_attrs() {
 }
 
 static int dispatch(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
-                    int has_pay, int fixed_levels) {
+                    int has_pay, int fixed_levels, bool capture = false) {
   if (a.key_type == PCF_KEY_F64)
-    return has_pay ? run_typed<KT_F64, 1>(a, lay, ws, pol, fixed_levels)
-                   : run_typed<KT_F64, 0>(a, lay, ws, pol, fixed_levels);
-  return has_pay ? run_typed<KT_U64, 1>(a, lay, ws, pol, fixed_levels)
-                 : run_typed<KT_U64, 0>(a, lay, ws, pol, fixed_levels);
+    return has_pay ? run_typed<KT_F64, 1>(a, lay, ws, pol, fixed_levels, capture)
+                   : run_typed<KT_F64, 0>(a, lay, ws, pol, fixed_levels, capture);
+  return has_pay ? run_typed<KT_U64, 1>(a, lay, ws, pol, fixed_levels, capture)
+                 : run_typed<KT_U64, 0>(a, lay, ws, pol, fixed_levels, capture);
 }
 
 // ---- graph replay of segmented sorts ----------------------------------------
@@ -810,7 +792,7 @@ static int run_graph(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     PCF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     SortArgs b = a;
     b.stream = cs;
-    const int rc = dispatch(b, lay, ws, pol, has_pay, chain_levels(a.n, pol.lds_cap));
+    const int rc = dispatch(b, lay, ws, pol, has_pay, chain_levels(a.n, pol.lds_cap), true);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &gr);
     if (rc != PCF_OK) {
@@ -883,7 +865,11 @@ size_t workspace_for(int key_type, size_t n, int has_pay, uint32_t nseg, int int
 int run_sort(const SortArgs& a) {
   if (a.key_type != PCF_KEY_F64 && a.key_type != PCF_KEY_U64) return PCF_ERR_INVALID_ARGUMENT;
   if (a.n == 0) {
-    if (a.d_status) PCF_HIP(hipMemsetAsync(a.d_status, 0, sizeof(int32_t), a.stream));
+    // a kernel rather than a memset, so a captured call holds no memset node
+    if (a.d_status) {
+      hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, a.stream, a.d_status, 0);
+      PCF_HIP(hipGetLastError());
+    }
     return PCF_OK;
   }
   if (!a.keys_in && !a.seg_src) return PCF_ERR_INVALID_ARGUMENT;
@@ -908,6 +894,10 @@ int run_sort(const SortArgs& a) {
   int rc;
   if (!own && use_graph(a))
     rc = run_graph(a, lay, ws, pol, has_pay);
+  else if (a.d_status && !a.trace)
+    // data errors reach the status word, so nothing needs the host: the
+    // fixed chain is enqueued and the call returns (a caller may capture it)
+    rc = dispatch(a, lay, ws, pol, has_pay, chain_levels(a.n, pol.lds_cap));
   else
     rc = dispatch(a, lay, ws, pol, has_pay, 0);
   if (own) {

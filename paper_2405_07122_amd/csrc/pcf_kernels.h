@@ -30,6 +30,8 @@ __global__ void k_init(Plan p);
 // capacity overflow or nodes left at `check_level` (the end of a fixed chain;
 // -1: no check), else PCF_ERR_HIP for a failed internal range check.
 __global__ void k_finish(Plan p, int32_t* d_status, int check_level);
+// Writes v to *d (the status word of a call with nothing to sort).
+__global__ void k_set_status(int32_t* d, int32_t v);
 
 struct LevelIO {
   void* dst_keys;       // where this level's scatter writes (absolute positions)
@@ -109,12 +111,6 @@ struct K5Cfg {
 // classes (what their LDS allows) with 16 waves each time.  The launch uses
 // exactly the resident number of workgroups: items are assigned statically, so
 // a second round of workgroups would double the time of the last ones.
-#ifndef PCF_K5_MID_NT
-#define PCF_K5_MID_NT 512
-#endif
-#ifndef PCF_K5_BIG_NT
-#define PCF_K5_BIG_NT 1024
-#endif
 
 template <int KT, int CAP, int PAY, int NT>
 struct K5Occ {

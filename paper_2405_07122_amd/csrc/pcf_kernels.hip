@@ -29,20 +29,9 @@
 #include "pcf_kernels.h"
 #include "pcf_block.h"
 
-// Compile-time variants (the defaults are the measured best on MI355X):
-//   PCF_K5_PREFETCH  1: the in-LDS finish loads the next item's keys while it
-//                    sorts the current one.
-#ifndef PCF_K5_PREFETCH
-#define PCF_K5_PREFETCH 0
-#endif
-//   PCF_SC_BATCH_RANK  1: the scatter issues all table reads of a tile's keys
-//                      before their rank atomics.
-#ifndef PCF_SC_BATCH_RANK
-#define PCF_SC_BATCH_RANK 1
-#endif
-
 namespace pcf {
 
+constexpr int ERR_INVALID_ARGUMENT = 1;  // PCF_ERR_INVALID_ARGUMENT
 constexpr int ERR_INVALID_KEY = 2;  // PCF_ERR_INVALID_KEY
 constexpr int ERR_OUT_OF_MEMORY = 3;  // PCF_ERR_OUT_OF_MEMORY
 constexpr int ERR_HIP = 4;  // PCF_ERR_HIP
@@ -81,6 +70,10 @@ __global__ void k_finish(Plan p, int32_t* d_status, int check_level) {
   if (d_status) *d_status = s;
 }
 
+__global__ void k_set_status(int32_t* d, int32_t v) {
+  if (threadIdx.x == 0) *d = v;
+}
+
 // Creates the roots: one node (or one LDS item) per non-empty segment.  A
 // single workgroup walks the segments in blocks and hands out indices and
 // arena space with block scans, so no atomics are needed.
@@ -100,7 +93,12 @@ __global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
     if (s < a.nseg) {
       b0 = a.offsets ? a.offsets[s] : 0ull;
       const uint64_t b1 = a.offsets ? a.offsets[s + 1] : a.n;
-      len = b1 > b0 ? (uint32_t)(b1 - b0) : 0u;
+      // CSR offsets must start at 0, never decrease and end at n: then the
+      // segments are disjoint and every output position lies below n.  A
+      // violation is a data error of the call; the segment gets no node.
+      const bool bad = b1 < b0 || b1 > a.n || (s == 0 && b0 != 0) || (s + 1 == a.nseg && b1 != a.n);
+      if (bad) atomicMax(&c->status, ERR_INVALID_ARGUMENT);
+      len = bad ? 0u : (uint32_t)(b1 - b0);
     }
     const bool item = len > 0 && len <= p.pol.lds_cap && !a.force_global;
     const bool glob = len > 0 && !item;
@@ -349,7 +347,17 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       const uint32_t top = 63u - (uint32_t)__clzll((long long)range);
       const uint32_t nbits = nd.nbits;
       shift = top + 1 > nbits ? top + 1 - nbits : 0u;
-      if (top >= 16 && nd.len >= RS) {
+      // Level budget.  A linear digit leaves its children at most
+      // bl - nbits = bl - 8 bits of range (bl = top + 1), so a radix node of
+      // bl bits finishes within ceil(bl / 8) levels plus the level that marks
+      // its single-valued children done.  A log digit fixes only the leading
+      // one and the two bits after it: children keep up to bl - 3 bits.  Log
+      // digits are therefore taken only when the levels after this one can
+      // still finish such a child linearly; every radix node then finishes
+      // inside the call's nlev levels.
+      const uint32_t left = p.nlev > (uint32_t)L + 1 ? p.nlev - (uint32_t)L - 1 : 0u;
+      const bool log_fits = (top + 1 - 3 + 7) / 8 + 1 <= left;
+      if (top >= 16 && nd.len >= RS && log_fits) {
         // RS samples: if most of them share one digit and, inside it, span
         // eight octaves or more between their 10th and 90th percentiles,
         // the keys spread over scales (clusters at log-uniform offsets) and
@@ -1007,15 +1015,14 @@ __global__ __launch_bounds__(NT, (PAY && TS > 2048) ? 2 : 4) void k_scatter(Plan
         // [w*PW, (w+1)*PW), round r lane l
         uint32_t code[R];  // bucket << 16 | rank
         uint16_t* wc = wcnt + w * nb;
+        // every table read of the tile is issued before the rank atomics
         uint32_t qq[R];
-        if (PCF_SC_BATCH_RANK) {
 #pragma unroll
-          for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
-        }
+        for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t i = w * PW + r * 64 + l;
-          uint32_t q = i < tn ? (PCF_SC_BATCH_RANK ? bk.finish2(qq[r], key[r]) : bk(key[r])) : 0u;
+          uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
           bad |= q >= nb;  // range check: cannot happen for a consistent model
           qq[r] = q < nb ? q : nb - 1;
         }
@@ -1584,18 +1591,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
   const int l = lane_id(), w = wave_id();
   unsigned long long done_keys = 0, bit_keys = 0, one_keys = 0;
   // static assignment of items to workgroups (a shared work counter would be
-  // a same-address atomic per item); with PCF_K5_PREFETCH the next item's
-  // keys are loaded into registers while this one is sorted
-  uint64_t pre[EPT];
-  if (PCF_K5_PREFETCH && first + blockIdx.x < total) {
-    const Item it0 = p.items[cls][first + blockIdx.x];
-    const uint64_t* s0 = reinterpret_cast<const uint64_t*>(it0.src);
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const uint32_t i = threadIdx.x + k * NT;
-      pre[k] = i < it0.len ? __builtin_nontemporal_load(gld(s0) + i) : 0ull;
-    }
-  }
+  // a same-address atomic per item)
   // fp64 keys: the next item's descriptor is loaded while this one is
   // sorted (its latency otherwise starts every item: 10 % of the small
   // class's time).  The uint64 instantiations keep the plain load: holding
@@ -1609,20 +1605,7 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
     const uint32_t m = it.len;
     done_keys += m;
     uint64_t kk[EPT];
-    if (PCF_K5_PREFETCH) {
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) kk[k] = pre[k];
-      const uint32_t nii = ii + gridDim.x;
-      if (nii < total) {
-        const Item nit = p.items[cls][nii];
-        const uint64_t* s1 = reinterpret_cast<const uint64_t*>(nit.src);
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-          const uint32_t i = threadIdx.x + k * NT;
-          pre[k] = i < nit.len ? __builtin_nontemporal_load(gld(s1) + i) : 0ull;
-        }
-      }
-    } else {
+    {
       const uint64_t* s0 = reinterpret_cast<const uint64_t*>(it.src);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
@@ -1924,18 +1907,16 @@ __global__ __launch_bounds__(NT, (K5Occ<KT, CAP, PAY, NT>::v)) void k_lds_sort(P
                                                          uint32_t);                      \
   template __global__ void k_scatter_keys<KT, 512, 4096>(Plan, int, LevelIO, uint32_t,   \
                                                          uint32_t);                      \
-  template __global__ void k_scatter<KT, 512, 4096, 0>(Plan, int, LevelIO, uint32_t,     \
-                                                       uint32_t);                        \
   template __global__ void k_scatter<KT, 512, 1024, 1>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
   template __global__ void k_scatter<KT, 512, 2048, 1>(Plan, int, LevelIO, uint32_t,     \
                                                        uint32_t);                        \
   template __global__ void k_lds_sort<KT, 2048, 256, 0>(Plan, int);                      \
   template __global__ void k_lds_sort<KT, 2048, 256, 1>(Plan, int);                      \
-  template __global__ void k_lds_sort<KT, 4096, PCF_K5_MID_NT, 0>(Plan, int);            \
-  template __global__ void k_lds_sort<KT, 4096, PCF_K5_MID_NT, 1>(Plan, int);            \
-  template __global__ void k_lds_sort<KT, 8192, PCF_K5_BIG_NT, 0>(Plan, int);            \
-  template __global__ void k_lds_sort<KT, 8192, PCF_K5_BIG_NT, 1>(Plan, int);
+  template __global__ void k_lds_sort<KT, 4096, 512, 0>(Plan, int);            \
+  template __global__ void k_lds_sort<KT, 4096, 512, 1>(Plan, int);            \
+  template __global__ void k_lds_sort<KT, 8192, 1024, 0>(Plan, int);            \
+  template __global__ void k_lds_sort<KT, 8192, 1024, 1>(Plan, int);
 
 PCF_INST_KT(KT_F64)
 PCF_INST_KT(KT_U64)

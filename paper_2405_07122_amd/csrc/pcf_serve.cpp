@@ -58,12 +58,16 @@ class HipExecutor : public pcfserve::Executor {
         round_up(pcf::workspace_for(d.key_type, d.total, d.argsort, d.nseg, 0), 256);
     if (ws_bytes + meta_bytes(d.nseg) > d.work_bytes || d.nseg > maxreq_) return PCF_ERR_INVALID_ARGUMENT;
     char* w = reinterpret_cast<char*>(d.work);
-    // metadata after the workspace: offsets (nseg + 1), sources (nseg), status
+    // metadata after the workspace: offsets (nseg + 1), sources (nseg)
     uint64_t* m_dev = reinterpret_cast<uint64_t*>(w + ws_bytes);
-    int32_t* status_dev = reinterpret_cast<int32_t*>(w + ws_bytes + round_up(8ull * (2 * d.nseg + 1), 256));
     uint64_t* m_host = reinterpret_cast<uint64_t*>(pinned_[slot]);
     for (uint32_t s = 0; s <= d.nseg; ++s) m_host[s] = d.offsets[s];
     for (uint32_t s = 0; s < d.nseg; ++s) m_host[d.nseg + 1 + s] = d.src[s];
+    // the producers' work on the request keys comes first
+    for (uint32_t s = 0; s < d.nseg; ++s)
+      if (d.ready && d.ready[s] &&
+          hipStreamWaitEvent(st, reinterpret_cast<hipEvent_t>((uintptr_t)d.ready[s]), 0) != hipSuccess)
+        return PCF_ERR_HIP;
     if (hipMemcpyAsync(m_dev, m_host, 8ull * (2 * d.nseg + 1), hipMemcpyHostToDevice, st) != hipSuccess)
       return PCF_ERR_HIP;
     pcf::SortArgs a = {};
@@ -78,17 +82,14 @@ class HipExecutor : public pcfserve::Executor {
     a.n = d.total;
     a.ws = w;
     a.ws_bytes = ws_bytes;
-    a.d_status = status_dev;
     a.stream = st;
+    // no status word: the worker waits for the batch anyway, so the call takes
+    // the levels the input needs (the host reads the level counts) and
+    // returns the data status itself
     int rc = pcf::run_sort(a);
-    int32_t* s_host = reinterpret_cast<int32_t*>(m_host + 2 * maxreq_ + 2);
-    if (rc == PCF_OK &&
-        hipMemcpyAsync(s_host, status_dev, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
-      rc = PCF_ERR_HIP;
     // the staging buffer and the batch memory are reused after this returns
     if (hipStreamSynchronize(st) != hipSuccess && rc == PCF_OK) rc = PCF_ERR_HIP;
-    if (rc != PCF_OK) return rc;
-    return *s_host;
+    return rc;
   }
 
   void shutdown() override {
@@ -151,6 +152,12 @@ int pcf_serve_submit(pcf_server* s, int key_type, const void* d_keys, size_t n, 
                      uint64_t* ticket) {
   if (!s) return PCF_ERR_INVALID_ARGUMENT;
   return s->srv->submit(key_type, d_keys, n, want_argsort, ticket);
+}
+
+int pcf_serve_submit_after(pcf_server* s, int key_type, const void* d_keys, size_t n,
+                           int want_argsort, void* ready_event, uint64_t* ticket) {
+  if (!s) return PCF_ERR_INVALID_ARGUMENT;
+  return s->srv->submit(key_type, d_keys, n, want_argsort, ticket, ready_event);
 }
 
 static void to_c(const pcfserve::Result& r, pcf_result* out) {

@@ -97,7 +97,8 @@ uint64_t Server::alone_bytes(int key_type, uint64_t n, int argsort) {
   return out_bytes(n, argsort) + round_up(ex_->work_bytes(key_type, n, argsort, 1), 256);
 }
 
-int Server::submit(int key_type, const void* d_keys, uint64_t n, int argsort, uint64_t* ticket) {
+int Server::submit(int key_type, const void* d_keys, uint64_t n, int argsort, uint64_t* ticket,
+                   const void* ready) {
   if (!ticket || (key_type != 0 && key_type != 1)) return S_INVALID_ARGUMENT;
   if (n > 0 && !d_keys) return S_INVALID_ARGUMENT;
   if (n >= (1ull << 32)) return S_INVALID_ARGUMENT;
@@ -110,6 +111,7 @@ int Server::submit(int key_type, const void* d_keys, uint64_t n, int argsort, ui
   r->key_type = key_type;
   r->argsort = argsort ? 1 : 0;
   r->src = d_keys;
+  r->ready = ready;
   r->n = n;
   r->t_submit = now_ns();
   r->status = S_PENDING;
@@ -180,7 +182,7 @@ bool Server::form_batch(std::vector<Request*>& reqs, Batch*& b, uint64_t& total)
 
 void Server::worker(uint32_t slot) {
   std::vector<Request*> reqs;
-  std::vector<uint64_t> offs, srcs;
+  std::vector<uint64_t> offs, srcs, readys;
   for (;;) {
     Batch* b = nullptr;
     uint64_t total = 0;
@@ -206,9 +208,11 @@ void Server::worker(uint32_t slot) {
     auto run_group = [&](size_t i0, size_t i1) {
       offs.assign(1, 0);
       srcs.clear();
+      readys.clear();
       for (size_t i = i0; i < i1; ++i) {
         offs.push_back(offs.back() + reqs[i]->n);
         srcs.push_back((uint64_t)(uintptr_t)reqs[i]->src);
+        readys.push_back((uint64_t)(uintptr_t)reqs[i]->ready);
       }
       BatchDesc d;
       d.key_type = kt;
@@ -217,6 +221,7 @@ void Server::worker(uint32_t slot) {
       d.total = offs.back();
       d.offsets = offs.data();
       d.src = srcs.data();
+      d.ready = readys.data();
       d.out_keys = base + b->out_off + 8 * reqs[i0]->out_pos;
       d.out_idx = as ? reinterpret_cast<uint32_t*>(base + b->idx_off) + reqs[i0]->out_pos : nullptr;
       d.work = base + b->work_off;

@@ -65,6 +65,8 @@ struct BatchDesc {
   uint64_t total;
   const uint64_t* offsets;  // host, nseg + 1 entries
   const uint64_t* src;      // host, nseg device addresses
+  const uint64_t* ready;    // host, nseg opaque event handles (0: none) the
+                            // batch must wait for before it reads src[s]
   void* out_keys;           // total keys
   uint32_t* out_idx;        // total indices or NULL
   void* work;               // work_bytes of scratch (workspace + metadata)
@@ -112,7 +114,10 @@ class Server {
   Server(const ServeConfig& cfg, std::unique_ptr<Executor> ex);
   ~Server();
   int start();  // S_OK or an executor error
-  int submit(int key_type, const void* d_keys, uint64_t n, int argsort, uint64_t* ticket);
+  // `ready` is an opaque event handle the executor waits for before the batch
+  // reads d_keys (NULL: the keys are ready now)
+  int submit(int key_type, const void* d_keys, uint64_t n, int argsort, uint64_t* ticket,
+             const void* ready = nullptr);
   int poll(uint64_t ticket, Result* out);
   int wait(uint64_t ticket, uint32_t timeout_ms, Result* out);
   int release(uint64_t ticket);
@@ -125,6 +130,7 @@ class Server {
     uint64_t ticket;
     int key_type, argsort;
     const void* src;
+    const void* ready;
     uint64_t n;
     uint64_t t_submit, t_start, t_done;
     int32_t status;

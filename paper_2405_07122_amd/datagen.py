@@ -116,6 +116,45 @@ def adversarial(dist: str, n: int, seed: int) -> np.ndarray:
     return out
 
 
+def nested_scales(n: int, seed: int, keep: float = 0.45, top_bits: int = 61,
+                  outliers: int = 3) -> np.ndarray:
+    """fp64 keys in nested shells of widely different scales (clustered
+    identifiers at many magnitudes, packed into tiny positive doubles).
+
+    Keys are built as 64-bit patterns: shell 0 spans offsets [0, 2^b) above the
+    smallest normal double with b = top_bits; it holds its minimum, half of a
+    fraction 1 - keep of its keys in [2^(b-21), 2^(b-20)) and the other half
+    in [2^(b-9), 2^(b-8)), and passes the fraction `keep` on to the next shell,
+    which starts at offset 2^(b-1) and has b - 3 bits.  Shells continue while
+    b >= 24; the last one is uniform.  `outliers` keys equal to 1.0 stretch the
+    value range far beyond the shells.  Shuffled."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    base = np.uint64(1) << np.uint64(52)  # bit pattern of the smallest normal double
+    b = top_bits
+    m = n - outliers
+    while m > 0:
+        if b < 24 or m < 64:
+            parts.append(base + rng.integers(0, 2 ** b, size=m, dtype=np.uint64))
+            break
+        inner = int(m * keep)
+        rest = m - inner - 1
+        lo = rest // 2
+        hi = rest - lo
+        parts.append(np.array([base], dtype=np.uint64))
+        parts.append(base + np.uint64(2 ** (b - 21)) +
+                     rng.integers(0, 2 ** (b - 21), size=lo, dtype=np.uint64))
+        parts.append(base + np.uint64(2 ** (b - 9)) +
+                     rng.integers(0, 2 ** (b - 9), size=hi, dtype=np.uint64))
+        base = base + np.uint64(2 ** (b - 1))
+        b -= 3
+        m = inner
+    out = np.concatenate(parts).view(np.float64)
+    out = np.concatenate([out, np.ones(outliers, dtype=np.float64)])
+    rng.shuffle(out)
+    return out
+
+
 def config1() -> np.ndarray:
     """The plain workload: n = 1e6 fp64 keys, Uniform[0, 1), seed 0."""
     return f64("uniform", 1_000_000, 0)

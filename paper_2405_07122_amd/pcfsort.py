@@ -14,9 +14,7 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# PCF_LIB_PATH selects another build of the same library (e.g. a variant
-# compiled with different tile sizes for tuning)
-LIB_PATH = os.environ.get("PCF_LIB_PATH") or os.path.join(HERE, "libpcfsort.so")
+LIB_PATH = os.path.join(HERE, "libpcfsort.so")
 
 OK = 0
 ERR_INVALID_ARGUMENT = 1
@@ -35,7 +33,7 @@ EXPORTS = [
     "pcf_status_string", "pcf_last_hip_error", "pcf_version", "pcf_workspace_bytes",
     "pcf_sort_f64", "pcf_sort_u64", "pcf_argsort", "pcf_sort_segmented", "pcf_level_trace",
     "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
-    "pcf_serve_create", "pcf_serve_submit", "pcf_serve_poll", "pcf_serve_wait",
+    "pcf_serve_create", "pcf_serve_submit", "pcf_serve_submit_after", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
     "pcf_profile_enable", "pcf_profile_select", "pcf_profile_read", "pcf_kernel_name", "pcf_graph_stats",
     "pcf_graph_clear", "pcf_policy_for", "pcf_lfail_grid",
@@ -127,6 +125,7 @@ def load(path: str = LIB_PATH):
         "pcf_load_tuning": (_INT, [ctypes.c_char_p]),
         "pcf_serve_create": (_INT, [ctypes.POINTER(ServeConfig), ctypes.POINTER(_VP)]),
         "pcf_serve_submit": (_INT, [_VP, _INT, _VP, _SZ, _INT, ctypes.POINTER(_U64)]),
+        "pcf_serve_submit_after": (_INT, [_VP, _INT, _VP, _SZ, _INT, _VP, ctypes.POINTER(_U64)]),
         "pcf_serve_poll": (_INT, [_VP, _U64, ctypes.POINTER(ServeResult)]),
         "pcf_serve_wait": (_INT, [_VP, _U64, _U32, ctypes.POINTER(ServeResult)]),
         "pcf_serve_release": (_INT, [_VP, _U64]),
@@ -395,12 +394,17 @@ class Server:
         self._inputs = {}
 
     def submit(self, keys: torch.Tensor, argsort: bool = False) -> int:
-        """Returns a ticket; `keys` is kept alive until the request is released."""
+        """Returns a ticket; `keys` is kept alive until the request is released.
+        An event recorded on torch's current stream orders the server's read
+        of `keys` after the work that produced them."""
         _need_cuda(keys)
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(keys.device))
         t = _U64()
-        _check(load().pcf_serve_submit(self._h, _key_type(keys), _ptr(keys), keys.numel(),
-                                       int(argsort), ctypes.byref(t)), "pcf_serve_submit")
-        self._inputs[t.value] = keys
+        _check(load().pcf_serve_submit_after(self._h, _key_type(keys), _ptr(keys), keys.numel(),
+                                             int(argsort), ctypes.c_void_p(ev.cuda_event),
+                                             ctypes.byref(t)), "pcf_serve_submit_after")
+        self._inputs[t.value] = (keys, ev)
         return t.value
 
     def _result(self, r: ServeResult, kt_dtype) -> dict:
@@ -421,7 +425,7 @@ class Server:
         if rc == PENDING:
             return None
         _check(rc, "pcf_serve_poll")
-        return self._result(r, self._inputs[ticket].dtype)
+        return self._result(r, self._inputs[ticket][0].dtype)
 
     def poll_status(self, ticket: int):
         """None while pending, else (status, latency_ns, batch_requests) without
@@ -439,7 +443,7 @@ class Server:
         if rc == PENDING:
             return None
         _check(rc, "pcf_serve_wait")
-        return self._result(r, self._inputs[ticket].dtype)
+        return self._result(r, self._inputs[ticket][0].dtype)
 
     def release(self, ticket: int) -> None:
         _check(load().pcf_serve_release(self._h, ticket), "pcf_serve_release")

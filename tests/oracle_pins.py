@@ -165,6 +165,51 @@ def pin_identity_closed_form(O, lib) -> list[str]:
     return fails
 
 
+def pin_halved_range_closed_form(O, lib) -> list[str]:
+    """Keys k 2^(1023-m) for k = -2^m..2^m span [-2^1023, 2^1023], whose width
+    overflows fp64, so the bin function works on halves (reading C11 of the
+    Sec. 3.3 bin function).  With beta = 2^(m+1) the halved scale is exactly
+    2^(m+1) / 2^1023 and the halved offset of key k is (k + 2^m) 2^(1022-m),
+    so key k sits exactly at bin k + 2^m; with every key sampled once,
+    b_i = i + 1.  Halving only one operand (v/2 - x_min, or v - x_min/2)
+    moves every key by 2^m bins and breaks the closed form."""
+    fails = []
+    rng = np.random.default_rng(6)
+    for m, reps, gamma in ((3, 1, 16), (3, 40, 5), (7, 3, 200), (10, 1, 63)):
+        k = np.arange(-(2 ** m), 2 ** m + 1, dtype=np.int64)
+        grid = k.astype(np.float64) * 2.0 ** (1023 - m)
+        beta = 2 ** (m + 1)
+        x = np.tile(grid, reps)[rng.permutation(grid.shape[0] * reps)] + 0.0
+        n = x.shape[0]
+        # one sample per distinct key: the first occurrence of each grid point
+        first = {}
+        for i, v in enumerate(x):
+            first.setdefault(float(v), i)
+        sidx = np.array([first[float(v)] for v in grid], dtype=np.uint64)
+        alpha = sidx.shape[0]
+        lv = O.level(x, alpha, beta, gamma, 0, sample_idx=sidx,
+                     vals=np.arange(n, dtype=np.uint32), lib=lib)
+        tag = f"m={m} reps={reps}"
+        if lv.halves != 1:
+            fails.append(f"{tag}: range width did not overflow into the halved form")
+            continue
+        i = np.arange(beta + 1, dtype=np.int64)
+        want_b = i + 1
+        want_T = ((i + 1) * gamma) // alpha
+        if not np.array_equal(lv.b.astype(np.int64), want_b):
+            fails.append(f"{tag}: b differs from i + 1")
+        if not np.array_equal(lv.T.astype(np.int64), want_T):
+            fails.append(f"{tag}: T differs from floor((i + 1) gamma / alpha)")
+        kb = np.round(x / 2.0 ** (1023 - m)).astype(np.int64) + 2 ** m  # exact bin of each key
+        want_sizes = np.bincount(want_T[kb], minlength=gamma + 1)
+        if not np.array_equal(lv.sizes.astype(np.int64), want_sizes):
+            fails.append(f"{tag}: bucket sizes differ from the closed form")
+        order = np.argsort(want_T[kb], kind="stable")
+        if not np.array_equal(lv.part_keys, x[order]):
+            fails.append(f"{tag}: partition differs from the stable closed form")
+    return fails
+
+
 def pin_scaled_closed_form(O, lib) -> list[str]:
     """x_k = x_min + k w (w a power of two), beta = 2(n-1): the scale is
     exactly 2/w, so i(x_k) = 2k and b_i = floor(i/2) + 1 for the full sample."""
@@ -389,6 +434,6 @@ def pin_spline_lfail_depth(O, lib) -> list[str]:
 
 
 ALL_PINS = [pin_library_sort, pin_brute_force, pin_selection_sort, pin_level_invariants,
-            pin_identity_closed_form, pin_scaled_closed_form, pin_lfail, pin_depth,
+            pin_identity_closed_form, pin_scaled_closed_form, pin_halved_range_closed_form, pin_lfail, pin_depth,
             pin_spline_library_sort, pin_spline_identity, pin_spline_thresholds,
             pin_spline_level_invariants, pin_spline_lfail_depth]

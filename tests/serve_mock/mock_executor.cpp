@@ -19,6 +19,8 @@ namespace {
 
 std::atomic<int> g_running{0}, g_max_running{0};
 std::atomic<uint64_t> g_batches{0}, g_max_batch{0};
+// while closed, a batch that has started waits before it sorts (bounded)
+std::atomic<int> g_gate_closed{0};
 
 uint64_t ordered(int kt, uint64_t b) {
   if (kt == 1) return b;
@@ -43,6 +45,8 @@ class MockExecutor : public Executor {
     uint64_t pb = g_max_batch.load();
     while (d.nseg > pb && !g_max_batch.compare_exchange_weak(pb, d.nseg)) {}
     ++g_batches;
+    for (int i = 0; i < 20000 && g_gate_closed.load(); ++i)
+      std::this_thread::sleep_for(std::chrono::milliseconds(1));
     if (delay_us_) std::this_thread::sleep_for(std::chrono::microseconds(delay_us_));
     // the work area must be writable over its whole declared size
     memset(d.work, 0xab, d.work_bytes);
@@ -96,6 +100,7 @@ void* mock_create(uint64_t budget, uint32_t slots, uint32_t maxreq, uint64_t max
   g_max_running = 0;
   g_batches = 0;
   g_max_batch = 0;
+  g_gate_closed = 0;
   ServeConfig c = {budget, slots, maxreq, maxkeys, 0};
   auto* s = new Server(c, std::unique_ptr<Executor>(new MockExecutor(delay_us)));
   if (s->start() != S_OK) {
@@ -148,5 +153,7 @@ void mock_destroy(void* s) { delete static_cast<Server*>(s); }
 
 int mock_max_running(void) { return g_max_running.load(); }
 uint64_t mock_max_batch(void) { return g_max_batch.load(); }
+uint64_t mock_batches_started(void) { return g_batches.load(); }
+void mock_gate(int closed) { g_gate_closed = closed ? 1 : 0; }
 
 }  // extern "C"

@@ -1,12 +1,14 @@
-"""Calls that only enqueue (a device status word is given) and the host's
-read of the control block after the planned levels.
+"""Calls that only enqueue (a device status word is given: a fixed chain of
+levels, no host read) and calls that wait (the host reads the control block
+after the planned levels).
 
 - An input that needs more global levels than the delta rule plans (multi-
-  scale u64 clusters take radix levels) runs a second LDS-finish pass for the
-  items of those levels; the output matches the oracle with and without the
-  status word.
+  scale u64 clusters take radix levels): a waiting call runs a second
+  LDS-finish pass for the items of those levels, an enqueue-only call runs
+  them inside its chain; the output matches the oracle both ways.
 - Profile figures of calls that only enqueue are folded in at
-  pcf_profile_read and equal those of calls that wait.
+  pcf_profile_read; they count the same keys per kernel as calls that wait
+  (the chain's empty levels add launches, not keys).
 - A data error reaches the status word of a call given one."""
 import numpy as np
 import pytest
@@ -99,7 +101,7 @@ def test_deferred_profile_equals_waiting_profile(P):
     assert int(st.item()) == 0
     wait, enq = figs
     for k in wait:
-        assert wait[k]["launches"] == enq[k]["launches"], k
+        assert enq[k]["launches"] >= wait[k]["launches"], k
         assert wait[k]["keys"] == enq[k]["keys"], k
         if wait[k]["launches"]:
             assert enq[k]["ms"] > 0, k
@@ -113,12 +115,8 @@ def test_status_word_of_enqueue_only_call(P):
     x[777] = np.nan
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     d = to_dev(x)
-    # the error reaches the status word; the call may also return it, when
-    # the host reads the control block after the planned levels
-    try:
-        P.pcf_sort_f64(d, d_status=st)
-    except P.PcfError as e:
-        assert e.code == P.ERR_INVALID_KEY
+    # the error reaches the status word; the call itself returns after enqueue
+    P.pcf_sort_f64(d, d_status=st)
     torch.cuda.synchronize()
     assert int(st.item()) == P.ERR_INVALID_KEY
     # and a valid input afterwards clears it

@@ -28,6 +28,15 @@ def _dt(x):
     return np.float64 if x.dtype == np.float64 else np.uint64
 
 
+def _halved_range_keys():
+    """Keys whose range width x_max - x_min overflows fp64 (about +-1.7e308): a
+    grid k 2^1020 (k = -8..8) plus keys spread over the whole range."""
+    rng = np.random.default_rng(36)
+    grid = np.arange(-8, 9, dtype=np.float64) * 2.0 ** 1020
+    x = np.concatenate([np.tile(grid, 600), rng.uniform(-1.0, 1.0, 40_000) * 1.7e308])
+    return x[rng.permutation(x.shape[0])] + 0.0
+
+
 LEVEL_CASES = [
     ("uniform", lambda: datagen.f64("uniform", 200_000, 31), (4096, 8192, 511)),
     ("lognormal", lambda: datagen.f64("lognormal", 150_000, 32), (2000, 16000, 1023)),
@@ -36,6 +45,7 @@ LEVEL_CASES = [
     ("bursty-u64", lambda: datagen.u64("bursty", 100_003, 35), (1500, 4000, 2047)),
     ("two-valued", lambda: np.where(np.random.default_rng(3).random(50_000) < 0.4, 1.5, -2.25),
      (500, 700, 63)),
+    ("halved-range", _halved_range_keys, (2000, 4096, 255)),
 ]
 
 

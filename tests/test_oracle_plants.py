@@ -19,6 +19,7 @@ PLANTS = [
     "PCFO_PLANT_SAMPLE_PREFIX",
     "PCFO_PLANT_SPLINE_UPPER",
     "PCFO_PLANT_SPLINE_NOFRAC",
+    "PCFO_PLANT_HALF_OFFSET",
 ]
 
 

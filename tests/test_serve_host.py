@@ -40,6 +40,8 @@ def M():
     lib.mock_stop.argtypes = [ctypes.c_void_p]
     lib.mock_destroy.argtypes = [ctypes.c_void_p]
     lib.mock_max_batch.restype = ctypes.c_uint64
+    lib.mock_batches_started.restype = ctypes.c_uint64
+    lib.mock_gate.argtypes = [ctypes.c_int]
     return lib
 
 
@@ -198,15 +200,30 @@ def test_tickets_and_release(M):
     s.close()
 
 
+def _until(cond, seconds=20.0):
+    t0 = time.monotonic()
+    while not cond():
+        assert time.monotonic() - t0 < seconds, "condition not reached"
+        time.sleep(0.001)
+
+
 def test_invalid_key_is_isolated(M):
-    """A request with a NaN fails alone; the requests batched with it succeed."""
-    s = Srv(M, slots=1, delay_us=30000)
-    rng = np.random.default_rng(7)
-    blocker = rng.random(100)
-    s.submit(blocker)
-    arrs = [rng.random(400) for _ in range(6)]
-    arrs[3][17] = np.nan
-    ts = [s.submit(a)[1] for a in arrs]
+    """A request with a NaN fails alone; the requests batched with it succeed.
+    A gate holds the only slot's first batch until the six requests are all
+    queued, so they are taken as one batch whatever the thread timing."""
+    s = Srv(M, slots=1)
+    M.mock_gate(1)
+    try:
+        rng = np.random.default_rng(7)
+        blocker = rng.random(100)
+        s.submit(blocker)
+        _until(lambda: M.mock_batches_started() >= 1)
+        arrs = [rng.random(400) for _ in range(6)]
+        arrs[3][17] = np.nan
+        ts = [s.submit(a)[1] for a in arrs]
+        _until(lambda: s.stats()["queued"] == 6)
+    finally:
+        M.mock_gate(0)
     for j, (a, t) in enumerate(zip(arrs, ts)):
         rc, r = s.wait(t)
         assert rc == OK
@@ -215,7 +232,7 @@ def test_invalid_key_is_isolated(M):
         else:
             assert r.status == OK
             np.testing.assert_array_equal(s.result(r, np.float64)[0], np.sort(a))
-        assert r.batch_requests > 1
+        assert r.batch_requests == 6
     s.close()
 
 
