@@ -96,6 +96,24 @@ int pcf_sort_u64(const uint64_t *d_in, uint64_t *d_out, size_t n, void *d_ws, si
                  int32_t *d_status, void *stream);
 
 /*
+ * For callers that cannot allocate (code under hipGraph capture, tight
+ * serving loops, hosts that forbid allocation): pcf_sort_f64 with no
+ * workspace argument and no allocation of any kind.  The workspace is a
+ * static device array of PCF_STATIC_SCRATCH_BYTES that the library holds on
+ * every device it runs on, until the process ends.  n is limited to what that
+ * array holds (about 10 million keys; pcf_workspace_bytes(PCF_KEY_F64, n, 0, 1)
+ * must not exceed it): larger n returns PCF_ERR_OUT_OF_MEMORY and enqueues
+ * nothing.  d_status is required (PCF_ERR_INVALID_ARGUMENT if NULL): the call
+ * enqueues the fixed chain and returns; data errors reach *d_status.  Calls
+ * on one device share the one array, so calls that overlap on a device (on
+ * different streams, or on one stream reordered by the caller) race; calls in
+ * order on one stream do not.  Profile events are not recorded for it.
+ */
+#define PCF_STATIC_SCRATCH_BYTES (128ull << 20)
+int pcf_sort_f64_static(const double *d_in, double *d_out, size_t n, int32_t *d_status,
+                        void *stream);
+
+/*
  * Argsort (Algorithm 1 with each key carrying its input position).
  * d_idx_out[k] receives the input position of the k-th smallest key; ties
  * are broken by ascending position.  d_keys_out (nullable) receives the

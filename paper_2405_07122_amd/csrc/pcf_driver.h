@@ -63,6 +63,7 @@ struct SortArgs {
   uint64_t* h_scalars;
   // filled on return when not NULL
   uint32_t* levels_run;
+  int no_prof;             // record no profile events (they would be created on demand)
 };
 
 int run_sort(const SortArgs& a);

@@ -445,7 +445,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   pd.mid_cap = K5_MID_CAP;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    pd.prof = g_prof_on ? 1u : 0u;
+    pd.prof = (g_prof_on && !a.no_prof) ? 1u : 0u;
   }
   p.pol = pd;
   p.seed = (uint64_t)pol.seed;
@@ -483,7 +483,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
 
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    t_prof.start(st, g_prof_on, g_prof_mask);
+    t_prof.start(st, g_prof_on && !a.no_prof, g_prof_mask);
   }
   PCF_MARK(PCF_K_SETUP, 0, {
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, p);
@@ -907,6 +907,34 @@ int run_sort(const SortArgs& a) {
   return rc;
 }
 
+// ---- scratch of the allocation-free entry point ------------------------------
+// pcf_sort_f64_static takes its workspace from this array instead of a
+// caller buffer or a stream-ordered allocation.  Every device the library
+// runs on holds its own copy (at its own address) until the process ends.
+constexpr size_t STATIC_SCRATCH_BYTES = PCF_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[16] = {};  // device address of `scratch`, per device
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.  (In host code the array's name is only a
+// stand-in for the symbol; kernels are given this address.)
+static int static_scratch(void** out) {
+  int dev = 0;
+  PCF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 16) return PCF_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __LINE__);
+    if (!ptr) return PCF_ERR_HIP;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return PCF_OK;
+}
+
 }  // namespace pcf
 
 using namespace pcf;
@@ -1016,6 +1044,28 @@ int pcf_sort_f64(const double* d_in, double* d_out, size_t n, void* d_ws, size_t
 int pcf_sort_u64(const uint64_t* d_in, uint64_t* d_out, size_t n, void* d_ws, size_t ws_bytes,
                  int32_t* d_status, void* stream) {
   return sort_keys(PCF_KEY_U64, d_in, d_out, n, d_ws, ws_bytes, d_status, stream);
+}
+
+int pcf_sort_f64_static(const double* d_in, double* d_out, size_t n, int32_t* d_status,
+                        void* stream) {
+  if (!d_status || (n > 0 && (!d_in || !d_out))) return PCF_ERR_INVALID_ARGUMENT;
+  if (n > 0 && workspace_for(PCF_KEY_F64, n, 0, 1, 0) > STATIC_SCRATCH_BYTES)
+    return PCF_ERR_OUT_OF_MEMORY;  // beyond the static scratch
+  void* ws = nullptr;
+  const int r = static_scratch(&ws);
+  if (r != PCF_OK) return r;
+  SortArgs a = {};
+  a.key_type = PCF_KEY_F64;
+  a.keys_in = d_in;
+  a.keys_out = d_out;
+  a.nseg = 1;
+  a.n = n;
+  a.ws = ws;
+  a.ws_bytes = STATIC_SCRATCH_BYTES;
+  a.d_status = d_status;  // the fixed chain: no host read, no pinned buffer
+  a.no_prof = 1;          // profile events are created on demand: none here
+  a.stream = reinterpret_cast<hipStream_t>(stream);
+  return run_sort(a);
 }
 
 int pcf_argsort(int key_type, const void* d_keys_in, void* d_keys_out, uint32_t* d_idx_out,

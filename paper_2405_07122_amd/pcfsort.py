@@ -31,7 +31,7 @@ KEY_U64 = 1
 
 EXPORTS = [
     "pcf_status_string", "pcf_last_hip_error", "pcf_version", "pcf_workspace_bytes",
-    "pcf_sort_f64", "pcf_sort_u64", "pcf_argsort", "pcf_sort_segmented", "pcf_level_trace",
+    "pcf_sort_f64", "pcf_sort_u64", "pcf_sort_f64_static", "pcf_argsort", "pcf_sort_segmented", "pcf_level_trace",
     "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_submit_after", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
         "pcf_workspace_bytes": (_SZ, [_INT, _SZ, _INT, _U32]),
         "pcf_sort_f64": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
         "pcf_sort_u64": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+        "pcf_sort_f64_static": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
         "pcf_argsort": (_INT, [_INT, _VP, _VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
         "pcf_sort_segmented": (_INT, [_INT, _VP, _VP, _VP, _VP, _VP, _U32, _SZ, _VP, _SZ, _VP,
                                       _VP]),
@@ -220,6 +221,23 @@ def pcf_sort_u64(keys: torch.Tensor, out: torch.Tensor | None = None, ws=None, d
     wp, wb = _ws_args(ws)
     _check(lib.pcf_sort_u64(_ptr(keys), _ptr(out), keys.numel(), wp, wb, _ptr(d_status),
                             _stream(stream)), "pcf_sort_u64")
+    return out
+
+
+STATIC_SCRATCH_BYTES = 128 << 20  # PCF_STATIC_SCRATCH_BYTES
+
+
+def pcf_sort_f64_static(keys: torch.Tensor, d_status: torch.Tensor, out: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+    """pcf_sort_f64 with the library's static scratch as workspace (no
+    allocation by the library); `d_status` (int32 device tensor) is required."""
+    lib = load()
+    if keys.dtype != torch.float64:
+        raise TypeError("pcf_sort_f64_static needs float64 keys")
+    out = torch.empty_like(keys) if out is None else out
+    _need_cuda(keys, out, d_status)
+    _check(lib.pcf_sort_f64_static(_ptr(keys), _ptr(out), keys.numel(), _ptr(d_status),
+                                   _stream(stream)), "pcf_sort_f64_static")
     return out
 
 
