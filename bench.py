@@ -4,14 +4,16 @@
 A step is one full sort (every recursion level plus the in-LDS finish) of one
 n = 1e8 fp64 array; steps rotate over the six synthetic distributions
 (uniform, normal, lognormal, exponential, chi-squared(4), 8-Gaussian mixture;
-seeds 1-6), keys only.  Inputs are resident in HBM before the timed region.
-Prints one JSON line.  `roofline` prices the graded pass (the keys-only
-scatter, k_scatter_keys) against the 8 TB/s HBM peak from hipEvents recorded
-around every scatter launch inside the timed region; `cpu_baseline` is the CPU
-oracle on a bounded sample of the same keys, with std::sort beside it.  Extra
-legs: the spline model, the per-stage profile on normal and point-mass
-inputs, the serving trace, the segmented batch, and (with --lfail) the
-bucketing-failure experiment.
+seeds 1-6), keys only, each call waiting for its outcome.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.  `roofline`
+prices the graded pass (the keys-only scatter, k_scatter_keys) against the
+8 TB/s HBM peak from hipEvents recorded around every scatter launch inside
+the timed region; `cpu_baseline` is the CPU oracle on the bytes of one timed
+sort, with std::sort beside it.  Extra legs: the enqueue-only form of the
+same calls, argsort of the six arrays, the spline model, App. D's four-way
+runtime profile on normal and point-mass inputs, the serving trace, the
+segmented batch, the skewed uint64 workload at 2e8 keys, and (with --lfail)
+the bucketing-failure experiment.
 """
 from __future__ import annotations
 
@@ -93,21 +95,29 @@ def host_cpu() -> dict:
     return {"cpu": model, "nproc": os.cpu_count()}
 
 
-def cpu_baseline(x, sample: int):
-    """The CPU oracle, as it stands, on the first `sample` keys; std::sort on
-    the same keys beside it (one thread each)."""
+def cpu_baseline(x, reps: int):
+    """The CPU oracle, as it stands, on exactly the bytes of one timed GPU sort
+    (the whole uniform seed-1 array), `reps` runs on one thread (median and
+    minimum); std::sort on the same keys beside it."""
+    import numpy as np
+
     from oracle import oracle
-    xs = x[:sample].copy()
     oracle.load()
-    t0 = time.perf_counter()
-    out, _, _ = oracle.sort(xs)
-    dt = time.perf_counter() - t0
-    st = oracle.stdsort_seconds(xs)
-    return {"value": sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} keys of the uniform seed-1 array (fp64), "
-                      f"single thread, {dt:.2f} s",
-            "std_sort": {"value": sample / st, "unit": "keys/s", "cores": 1,
-                         "seconds": st},
+    ot, stt = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out, _, _ = oracle.sort(x)
+        ot.append(time.perf_counter() - t0)
+        del out
+        stt.append(oracle.stdsort_seconds(x))
+    n = x.shape[0]
+    om, smed = float(np.median(ot)), float(np.median(stt))
+    return {"value": n / om, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole uniform seed-1 array ({n} fp64 keys, the bytes of one timed "
+                      f"sort), single thread, {reps} runs: median {om:.2f} s, min {min(ot):.2f} s",
+            "median_s": om, "min_s": float(min(ot)), "runs": reps,
+            "std_sort": {"value": n / smed, "unit": "keys/s", "cores": 1, "median_s": smed,
+                         "min_s": float(min(stt)), "runs": reps},
             "host": host_cpu()}
 
 
@@ -284,17 +294,22 @@ def served_leg(P, dev: dict, rates, count: int, budget: int, streams: int):
 
 
 def stages_leg(P, n: int, reps: int = 3):
-    """Per-stage breakdown (the paper's runtime profile, App. D) for normal
-    keys and for the point-mass input of App. C (n normal keys + n copies of
-    one in-range value), keys only.  Stages: training (fit), bucketing (range,
-    count, column scan, classify, scatter), in-LDS finish; beside them the
-    share of keys (summed over levels) that the standard sort of failed
-    buckets handled (radix levels, bitonic in LDS) and that single-value
-    exits retired."""
+    """The paper's runtime profile (App. D): for normal keys and for the
+    point-mass input of App. C (n normal keys + n copies of one in-range
+    value), keys only, the time of (i) model training (fit), (ii) bucketing
+    (range, count, column scan, classify, scatter), (iii) the sort of buckets
+    that recursed down to the LDS finish (small buckets: in-LDS PCF levels and
+    their counting rank), (iv) the standard sort of failed buckets
+    (|c_j| >= delta: radix levels and the bitonic sort in LDS).  Time of a
+    launch that mixes model nodes and failed buckets is apportioned by key
+    share (fallback_ms of the profile).  Beside them: the share of keys
+    (summed over levels) that the failed-bucket sort and single-value exits
+    handled."""
     import torch
 
     from paper_2405_07122_amd import datagen
     res = {}
+    level = ("range", "count", "colscan", "classify", "scatter")
     for name, gen in (("normal", lambda: datagen.f64("normal", 2 * n, 2)),
                       ("point_mass", lambda: datagen.adversarial("normal", n, 2))):
         x = torch.from_numpy(gen()).to("cuda")
@@ -305,6 +320,7 @@ def stages_leg(P, n: int, reps: int = 3):
         ref, _ = torch.sort(x)
         if not torch.equal(out, ref):
             raise RuntimeError(f"stages: {name} output differs from torch.sort")
+        P.pcf_profile_select(None)
         P.pcf_profile_enable(True)
         P.pcf_profile_read(reset=True)
         t0 = time.perf_counter()
@@ -315,19 +331,96 @@ def stages_leg(P, n: int, reps: int = 3):
         pr = P.pcf_profile_read(reset=True)
         P.pcf_profile_enable(False)
         ms = {k: v["ms"] / reps for k, v in pr.items()}
+        fb = {k: v["fallback_ms"] / reps for k, v in pr.items()}
         keys = {k: v["keys"] / reps / x.numel() for k, v in pr.items()}
         res[name] = {
-            "keys": x.numel(), "ms_per_sort": dt * 1e3,
-            "training_ms": ms["fit"],
-            "bucketing_ms": ms["range"] + ms["count"] + ms["colscan"] + ms["classify"] +
-                            ms["scatter"],
-            "lds_finish_ms": ms["lds_small"] + ms["lds_big"],
-            "setup_ms": ms["setup"],
+            "keys": x.numel(), "ms_per_sort": dt * 1e3, "setup_ms": ms["setup"],
+            "i_training_ms": ms["fit"] - fb["fit"],
+            "ii_bucketing_ms": sum(ms[k] - fb[k] for k in level),
+            "iii_small_bucket_sort_ms": ms["lds_small"] + ms["lds_big"] - fb["lds_small"]
+                                        - fb["lds_big"],
+            "iv_failed_bucket_sort_ms": sum(fb.values()),
             "radix_key_share": keys["radix_keys"], "bitonic_key_share": keys["bitonic_keys"],
             "single_value_key_share": keys["single_keys"]}
-        del x, out, ws
+        del x, out, ws, ref
     torch.cuda.empty_cache()
     return res
+
+
+def argsort_leg(P, dev: dict, reps: int = 3):
+    """Single-array argsort workload: each n = 1e8 fp64 array with a uint32
+    index payload (positions synthesized on the first level), stable; each
+    output checked against torch's stable sort outside the timed runs."""
+    import numpy as np
+    import torch
+    n = next(iter(dev.values())).numel()
+    ko = torch.empty(n, dtype=torch.float64, device="cuda")
+    io = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = P.workspace(P.KEY_F64, n, with_payload=True)
+    per = {}
+    total_t = 0.0
+    for d, x in dev.items():
+        P.pcf_argsort(x, keys_out=ko, idx_out=io, ws=ws)
+        torch.cuda.synchronize()
+        rv, ri = torch.sort(x, stable=True)
+        if not (torch.equal(ko, rv) and torch.equal(io.to(torch.int64), ri)):
+            raise RuntimeError(f"argsort {d}: differs from torch's stable sort")
+        del rv, ri
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            P.pcf_argsort(x, keys_out=ko, idx_out=io, ws=ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        per[d] = {"median_ms": float(np.median(ts)) * 1e3, "min_ms": float(min(ts)) * 1e3}
+        total_t += float(np.median(ts))
+    del ko, io, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"pcf_argsort n={n} fp64 + uint32 positions, six distributions "
+                        f"(seeds 1-6), checked against torch.sort(stable=True)",
+            "keys_per_s": len(dev) * n / total_t, "per_distribution": per, "reps": reps}
+
+
+def u64_leg(P, n: int, reps: int = 3):
+    """Skewed uint64 workload (n keys each): heavy duplicates (Zipf s=1.1 over
+    2e6 distinct values, seed 7), clustered identifiers (1000 runs at
+    log-uniform offsets, seed 8), bursty timestamps (Pareto(1.5) increments,
+    seed 9).  Each output is checked to be non-decreasing as unsigned
+    integers and equal to torch's sort of the input (keys mapped to signed
+    order by flipping the top bit)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_07122_amd import datagen
+    res = {}
+    top = torch.tensor(np.iinfo(np.int64).min, dtype=torch.int64, device="cuda")
+    for kind in datagen.U64_KINDS:
+        log(f"u64 {kind}: generating {n} keys")
+        x = torch.from_numpy(datagen.config3(kind, n).view(np.int64)).to("cuda")
+        out = torch.empty_like(x)
+        ws = P.workspace(P.KEY_U64, n)
+        P.pcf_sort_u64(x, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ys = out ^ top
+        if not bool((ys[1:] >= ys[:-1]).all()):
+            raise RuntimeError(f"u64 {kind}: output not ascending")
+        rs, _ = torch.sort(x ^ top)
+        if not torch.equal(rs, ys):
+            raise RuntimeError(f"u64 {kind}: output is not the sorted input")
+        del ys, rs
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            P.pcf_sort_u64(x, out=out, ws=ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        res[kind] = {"median_ms": med * 1e3, "min_ms": float(min(ts)) * 1e3,
+                     "keys_per_s": n / med, "seed": datagen.U64_SEEDS[kind]}
+        del x, out, ws
+        torch.cuda.empty_cache()
+    return {"workload": f"pcf_sort_u64 n={n}, zipf / clustered / bursty", "n": n, "kinds": res,
+            "reps": reps}
 
 
 def lfail_leg(P, n: int = 1_000_000, reps: int = 100):
@@ -395,9 +488,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--dists", default="all")
-    ap.add_argument("--cpu-sample", type=int, default=30_000_000)
+    ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--argsort", action="store_true", help="also time argsort (untimed leg)")
+    ap.add_argument("--no-argsort", action="store_true", help="skip the argsort leg")
+    ap.add_argument("--no-u64", action="store_true", help="skip the uint64 leg")
+    ap.add_argument("--u64-n", type=int, default=200_000_000)
     ap.add_argument("--no-batched", action="store_true", help="skip the segmented leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage profile leg")
@@ -466,9 +561,12 @@ def main():
     pcfsort.pcf_profile_enable(True)
     pcfsort.pcf_profile_read(reset=True)
     torch.cuda.synchronize()
+    step_s = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws)
+        ts = time.perf_counter()
+        pcfsort.pcf_sort_f64(dev[dists[k % len(dists)]], out=out, ws=ws)  # waits for its outcome
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = pcfsort.pcf_profile_read(reset=True)
@@ -529,17 +627,12 @@ def main():
                            "model": "spline (App. A.5) on the global levels"}
         pcfsort.set_policy(**base)
         del wsp
-    if args.argsort:
-        idx = torch.empty(n, dtype=torch.int32, device="cuda")
-        wsa = pcfsort.workspace(pcfsort.KEY_F64, n, with_payload=True)
-        pcfsort.pcf_argsort(dev[dists[0]], keys_out=out, idx_out=idx, ws=wsa)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        reps = 4
-        for k in range(reps):
-            pcfsort.pcf_argsort(dev[dists[k % len(dists)]], keys_out=out, idx_out=idx, ws=wsa)
-        torch.cuda.synchronize()
-        extra["argsort_keys_per_s"] = reps * n / (time.perf_counter() - ta)
+    if not args.no_argsort:
+        del ws
+        torch.cuda.empty_cache()
+        extra["argsort"] = argsort_leg(pcfsort, dev)
+        log(f"argsort: {extra['argsort']['keys_per_s']:.3e} keys/s")
+        ws = pcfsort.workspace(pcfsort.KEY_F64, n)
 
     if args.lfail:
         extra["lfail"] = lfail_leg(pcfsort)
@@ -552,14 +645,19 @@ def main():
         extra["served"] = served_leg(pcfsort, dev, [float(r) for r in args.served_rates.split(",")],
                                      args.served_count, 64 << 30, args.served_streams)
 
-    if not args.no_batched:
+    if not args.no_batched or not args.no_u64:
         del dev, out, ws
         torch.cuda.empty_cache()
+    if not args.no_batched:
         extra["batched"] = batched_leg(pcfsort, args.batched_reps, args.batched_segments)
+    if not args.no_u64:
+        extra["u64"] = u64_leg(pcfsort, args.u64_n)
+        log(f"u64: {extra['u64']['kinds']}")
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(host[dists[0]], min(args.cpu_sample, n))
+        log("cpu baseline: oracle and std::sort on the uniform array")
+        cpu = cpu_baseline(host[dists[0]], args.cpu_reps)
 
     line = {
         "metric": "keys/s & % HBM roofline at n=1e8 fp64",
@@ -569,6 +667,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3,
+        "step_ms": {"median": float(np.median(step_s)) * 1e3, "min": float(min(step_s)) * 1e3},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -218,6 +218,11 @@ typedef struct {
     uint64_t launches;
     double ms;    /* summed hipEvent elapsed time */
     double keys;  /* summed keys processed by the launches */
+    /* part of ms spent on the standard sort of failed buckets (|c_j| >= delta,
+     * Algorithm 1), apportioned by key share: on a global level, ms times the
+     * level's keys in radix nodes over its keys; in the LDS finish, ms times
+     * the bitonic-sorted keys over the keys of the LDS items */
+    double fallback_ms;
 } pcf_kernel_stat;
 
 int pcf_profile_enable(int on);

@@ -206,7 +206,8 @@ struct Item {
 struct LevelCtr {
   uint32_t num_nodes, num_units, aux_used, pad;
   unsigned long long table_used, cm_used;
-  unsigned long long keys;  // keys in the level's nodes
+  unsigned long long keys;        // keys in the level's nodes
+  unsigned long long radix_keys;  // of those, keys in radix nodes (profiling)
 };
 
 struct Ctl {

@@ -165,14 +165,22 @@ struct CallProf {
       float ms = 0.f;
       PCF_HIP(hipEventElapsedTime(&ms, marks[i].a, marks[i].b));
       const int k = marks[i].kind, L = marks[i].level;
-      double keys = 0;
-      if (k == PCF_K_SETUP) keys = (double)n;
-      else if (k == PCF_K_LDS_SMALL) keys = (double)hc.item_keys[0];
-      else if (k == PCF_K_LDS_BIG) keys = (double)(hc.item_keys[1] + hc.item_keys[2]);
-      else keys = (double)hc.lv[L].keys;
+      double keys = 0, share = 0;
+      const double ik = (double)(hc.item_keys[0] + hc.item_keys[1] + hc.item_keys[2]);
+      if (k == PCF_K_SETUP) {
+        keys = (double)n;
+      } else if (k == PCF_K_LDS_SMALL || k == PCF_K_LDS_BIG) {
+        keys = k == PCF_K_LDS_SMALL ? (double)hc.item_keys[0]
+                                    : (double)(hc.item_keys[1] + hc.item_keys[2]);
+        share = ik > 0 ? std::min(1.0, (double)hc.bitonic_keys / ik) : 0.0;
+      } else {
+        keys = (double)hc.lv[L].keys;
+        if (k != PCF_K_RANGE && keys > 0) share = (double)hc.lv[L].radix_keys / keys;
+      }
       g_prof[k].launches += 1;
       g_prof[k].ms += ms;
       g_prof[k].keys += keys;
+      g_prof[k].fallback_ms += ms * share;
     }
     return PCF_OK;
   }

@@ -445,7 +445,10 @@ __global__ __launch_bounds__(NT) void k_fit(Plan p, int L, int trace) {
       }
     }
     if (threadIdx.x == 0) {
-      if (p.pol.prof && kind == NK_RADIX) atomicAdd(&c->radix_keys, (unsigned long long)nd.len);
+      if (p.pol.prof && kind == NK_RADIX) {
+        atomicAdd(&c->radix_keys, (unsigned long long)nd.len);
+        atomicAdd(&c->lv[L].radix_keys, (unsigned long long)nd.len);
+      }
       nd.kind = kind;
       nd.state = NS_ACTIVE;
       nd.shift = shift;

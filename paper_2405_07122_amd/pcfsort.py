@@ -63,7 +63,8 @@ class Policy(ctypes.Structure):
 
 
 class KernelStat(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("keys", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("keys", ctypes.c_double),
+                ("fallback_ms", ctypes.c_double)]
 
 
 class ServeConfig(ctypes.Structure):
@@ -380,11 +381,14 @@ def pcf_profile_select(kinds=None) -> None:
 
 
 def pcf_profile_read(reset: bool = False) -> dict:
-    """Per-kernel totals: {name: {"launches", "ms", "keys"}}."""
+    """Per-kernel totals: {name: {"launches", "ms", "keys", "fallback_ms"}}
+    (fallback_ms: the part of ms apportioned to the standard sort of failed
+    buckets by key share)."""
     arr = (KernelStat * len(KERNEL_KINDS))()
     _check(load().pcf_profile_read(arr, int(reset)), "pcf_profile_read")
     return {KERNEL_KINDS[i]: {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
-                              "keys": float(arr[i].keys)} for i in range(len(KERNEL_KINDS))}
+                              "keys": float(arr[i].keys), "fallback_ms": float(arr[i].fallback_ms)}
+            for i in range(len(KERNEL_KINDS))}
 
 
 # ---- serving ------------------------------------------------------------------

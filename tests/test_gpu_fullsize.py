@@ -3,9 +3,11 @@ configuration (default policy, caller workspace).
 
 At n = 1e8 the output is compared element by element with the CPU oracle for
 the uniform array, and with torch's sort (a library sort on the same device,
-independent of this library) for every distribution; argsort indices with
-torch's stable sort.  A 5e8-key array generated on the device checks the
-largest size."""
+independent of this library) for every distribution; argsort indices of
+every distribution with torch's stable sort.  The uint64 kinds run at 2e8
+keys.  The batched workload (2048 segments, about 1.09e9 keys with a uint32
+payload) is compared per segment with torch's stable sorts (by key, then by
+segment).  A 5e8-key array generated on the device checks the largest size."""
 import numpy as np
 import pytest
 
@@ -50,7 +52,7 @@ def test_fullsize_uniform_vs_oracle(P, ws, oracle):
     np.testing.assert_array_equal(got, ref)
 
 
-@pytest.mark.parametrize("dist", ["normal", "lognormal"])
+@pytest.mark.parametrize("dist", datagen.F64_DISTS)
 def test_fullsize_argsort(P, ws, dist):
     import torch
     banner(f"full size argsort {dist}")
@@ -62,7 +64,7 @@ def test_fullsize_argsort(P, ws, dist):
 
 
 @pytest.mark.parametrize("kind,n", [("clustered", 200_000_000), ("bursty", 200_000_000),
-                                    ("zipf", 50_000_000)])
+                                    ("zipf", 200_000_000)])
 def test_fullsize_u64(P, kind, n):
     import torch
     banner(f"full size u64 {kind} n={n}")
@@ -74,6 +76,36 @@ def test_fullsize_u64(P, kind, n):
     flip = torch.tensor(-(2**63), dtype=torch.int64, device="cuda")
     ref, _ = torch.sort(x ^ flip)
     assert torch.equal(out ^ flip, ref)
+
+
+def test_fullsize_batched_segments(P, ws):
+    """The batched workload exactly as the benchmark runs it (graph path, caller
+    workspace), against an independent segmented stable sort built from two
+    stable torch sorts: by key, then by segment."""
+    import torch
+    keys, offsets, vals = datagen.segments(num=2048)
+    n = int(offsets[-1])
+    banner(f"full size batched: 2048 segments, {n} keys")
+    dk = to_dev(keys)
+    dv = to_dev(vals)
+    doff = to_dev(offsets.view(np.int64))
+    del keys, vals
+    wsb = P.workspace(P.KEY_F64, n, True, 2048)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ko, vo = P.pcf_sort_segmented(dk, doff, dv, ws=wsb, d_status=st)
+    torch.cuda.synchronize()
+    assert int(st.cpu()[0]) == 0
+    del wsb
+    _, p1 = torch.sort(dk, stable=True)
+    seg = torch.searchsorted(doff, torch.arange(n, device="cuda", dtype=torch.int64),
+                             right=True) - 1
+    _, p2 = torch.sort(seg[p1], stable=True)
+    del seg
+    perm = p1[p2]
+    del p1, p2
+    assert torch.equal(ko, dk[perm])
+    assert torch.equal(vo, dv[perm])
+    P.pcf_graph_clear()
 
 
 def test_largest_size_device_generated(P):

@@ -119,3 +119,36 @@ def test_budget_and_invalid_key(P):
         for d in devs[:4]:
             srv.submit(d)
     time.sleep(0.01)
+
+
+def test_large_requests(P):
+    """Requests from the top of the serving size range (2^21 .. 2^26 keys), fp64
+    and uint64, keys only and argsort, submitted together: every result equals
+    torch's (stable) sort of the request."""
+    import torch
+    banner("serve: large requests")
+    sizes = [(1 << 21) + 3, (1 << 23) + 5, (1 << 24) - 7, (1 << 25) + 11, (1 << 26) - 1]
+    rng = np.random.default_rng(77)
+    reqs = []
+    for j, m in enumerate(sizes):
+        if j % 2 == 0:
+            x = datagen.f64(datagen.F64_DISTS[j], m, 900 + j)
+        else:
+            x = datagen.u64(datagen.U64_KINDS[j % 3], m, 900 + j, distinct=50_000)
+        reqs.append((to_dev(x), bool(rng.random() < 0.5) or j == 4))
+    flip = torch.tensor(-(2**63), dtype=torch.int64, device="cuda")
+    with P.Server(hbm_budget_bytes=16 << 30, max_streams=2, max_batch_requests=8,
+                  max_batch_keys=1 << 28) as srv:
+        tickets = [srv.submit(d, argsort=a) for d, a in reqs]
+        for (d, a), t in zip(reqs, tickets):
+            r = srv.wait(t)
+            assert r["status"] == 0
+            if d.dtype == torch.float64:
+                rk, ri = torch.sort(d, stable=True)
+                assert torch.equal(r["keys"], rk)
+            else:
+                rk, ri = torch.sort(d ^ flip, stable=True)
+                assert torch.equal(r["keys"] ^ flip, rk)
+            if a:
+                assert torch.equal(r["idx"].to(torch.int64), ri)
+            srv.release(t)
