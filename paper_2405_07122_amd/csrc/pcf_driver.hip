@@ -546,15 +546,15 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     // finish every small array inside LDS
     PCF_MARK(PCF_K_LDS_SMALL, 0,
              hipLaunchKernelGGL((k_lds_sort<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>),
-                                dim3(cus * K5Occ<KT, K5_SMALL_CAP, PAY, K5_SMALL_NT>::wg_per_cu()),
+                                dim3(cus * k5_wg_per_cu<KT, K5_SMALL_CAP, PAY, K5_SMALL_NT>()),
                                 dim3(K5_SMALL_NT), sizeof(K5Smem<KT, K5_SMALL_CAP, K5_SMALL_NT, PAY>), st,
                                 p, 0));
     PCF_MARK(PCF_K_LDS_BIG, 0, {
       hipLaunchKernelGGL((k_lds_sort<KT, K5_MID_CAP, K5_MID_NT, PAY>),
-                         dim3(cus * K5Occ<KT, K5_MID_CAP, PAY, K5_MID_NT>::wg_per_cu()),
+                         dim3(cus * k5_wg_per_cu<KT, K5_MID_CAP, PAY, K5_MID_NT>()),
                          dim3(K5_MID_NT), sizeof(K5Smem<KT, K5_MID_CAP, K5_MID_NT, PAY>), st, p, 1);
       hipLaunchKernelGGL((k_lds_sort<KT, K5_BIG_CAP, K5_BIG_NT, PAY>),
-                         dim3(cus * K5Occ<KT, K5_BIG_CAP, PAY, K5_BIG_NT>::wg_per_cu()), dim3(K5_BIG_NT),
+                         dim3(cus * k5_wg_per_cu<KT, K5_BIG_CAP, PAY, K5_BIG_NT>()), dim3(K5_BIG_NT),
                          sizeof(K5Smem<KT, K5_BIG_CAP, K5_BIG_NT, PAY>), st, p, 2);
     });
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, p, a.d_status, check_level);

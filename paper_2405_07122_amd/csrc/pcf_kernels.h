@@ -117,9 +117,7 @@ struct K5Occ {
   // waves per SIMD: classes of 8 keys per thread fit 4 (uint64 with a payload:
   // 3); 16 keys per thread need twice the registers
   static constexpr int v = (CAP / NT <= 8) ? ((PAY && KT == 1) ? 3 : 4) : 2;
-  static constexpr int wg_per_cu() {
-    return v * 4 / (NT / 64) > 0 ? v * 4 / (NT / 64) : 1;
-  }
+  static constexpr int by_waves() { return v * 4 / (NT / 64) > 0 ? v * 4 / (NT / 64) : 1; }
 };
 
 template <int KT, int CAP, int NT, int PAY>
@@ -135,6 +133,15 @@ struct K5Smem {
   uint32_t flag;
   uint32_t sh[4];
 };
+
+// Resident workgroups per CU of an in-LDS finish class: what the waves allow,
+// capped by what the 160 KiB of LDS holds.
+template <int KT, int CAP, int PAY, int NT>
+constexpr int k5_wg_per_cu() {
+  const int by_lds = (int)((160 * 1024) / sizeof(K5Smem<KT, CAP, NT, PAY>));
+  const int w = K5Occ<KT, CAP, PAY, NT>::by_waves();
+  return w < by_lds ? w : (by_lds > 0 ? by_lds : 1);
+}
 
 template <int KT, int NT>
 __global__ void k_range(Plan p);
