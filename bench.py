@@ -33,6 +33,8 @@ HBM_PEAK_GBS = 8000.0
 SCATTER_BYTES_KEYS = 16
 SCATTER_BYTES_PAYLOAD = 24
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scatter_traffic.json")
+# autotuner table for fp64 keys with a uint32 payload on MI355X (pcf_autotune)
+TUNING_PAYLOAD = os.path.join(ROOT, "paper_2405_07122_amd", "tuning", "mi355x_f64_payload.json")
 KERNEL_SOURCES = ["paper_2405_07122_amd/csrc/pcf_kernels.hip",
                   "paper_2405_07122_amd/csrc/pcf_device.h",
                   "paper_2405_07122_amd/csrc/pcf_block.h"]
@@ -171,15 +173,43 @@ def batched_leg(P, reps: int, num: int):
     same = bool(torch.equal(ko, ko2) and torch.equal(vo, vo2))
     if not same:
         raise RuntimeError("segmented output differs from the per-segment plain path")
+    del ko2, vo2
+    # the autotuned table (node parameters by segment / node size): a new
+    # graph is captured under it; the output must be the same bytes
+    tuned = None
+    if os.path.exists(TUNING_PAYLOAD):
+        P.pcf_load_tuning(TUNING_PAYLOAD)
+        try:
+            wst = P.workspace(P.KEY_F64, n, True, num)
+            ko3 = torch.empty_like(dk)
+            vo3 = torch.empty_like(dv)
+            P.pcf_sort_segmented(dk, doff, dv, keys_out=ko3, vals_out=vo3, ws=wst, d_status=st)
+            torch.cuda.synchronize()
+            if int(st.item()) != 0:
+                raise RuntimeError(f"tuned segmented status {int(st.item())}")
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                P.pcf_sort_segmented(dk, doff, dv, keys_out=ko3, vals_out=vo3, ws=wst, d_status=st)
+            torch.cuda.synchronize()
+            t_tuned = (time.perf_counter() - t0) / reps
+            if not (torch.equal(ko, ko3) and torch.equal(vo, vo3)):
+                raise RuntimeError("tuned segmented output differs from the default policy's")
+            tuned = {"table": os.path.relpath(TUNING_PAYLOAD, ROOT), "graph_ms": t_tuned * 1e3,
+                     "graph_keys_per_s": n / t_tuned, "speedup_vs_default": t_graph / t_tuned,
+                     "bit_identical_to_default": True}
+            del ko3, vo3, wst
+        finally:
+            P.pcf_load_tuning(None)
+            P.pcf_graph_clear()
     g = P.pcf_graph_stats()
-    del dk, dv, ko, vo, ko2, vo2, ws
+    del dk, dv, ko, vo, ws
     torch.cuda.empty_cache()
     return {"workload": f"{num} fp64 segments, sizes floor(2^U[10,22]), seed 10, uint32 "
                         f"payload = in-segment index, {n} keys",
             "keys": n, "graph_ms": t_graph * 1e3, "graph_keys_per_s": n / t_graph,
             "plain_loop_ms": t_plain * 1e3, "plain_loop_keys_per_s": n / t_plain,
             "speedup_vs_plain": t_plain / t_graph, "reps": reps, "bit_identical": same,
-            "graph_captures": g["captures"], "graph_replays": g["replays"]}
+            "tuned": tuned, "graph_captures": g["captures"], "graph_replays": g["replays"]}
 
 
 # fixed lower clips of the u64 request keys floor((x - L) * 2^32), per distribution

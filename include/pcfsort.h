@@ -263,6 +263,10 @@ typedef struct {
     uint32_t model;              /* CDF model of the global levels: 0 PCF (Sec. 3.3),
                                     1 spline (Spline Learned Sort, App. A.5); the
                                     in-LDS finish uses the PCF at one bin per key */
+    uint32_t scatter_tile;       /* keys per scatter tile: 0 = default (8192 keys
+                                    alone, 2048 with a payload); 4096 or 8192 for
+                                    keys alone, 1024 or 2048 with a payload (other
+                                    values take the default) */
 } pcf_policy;
 
 /* Current process-wide policy (defaults, or what pcf_set_policy / tuning set). */
@@ -270,14 +274,22 @@ int pcf_get_policy(pcf_policy *out);
 int pcf_set_policy(const pcf_policy *p);
 
 /* The policy a call of n keys uses: the loaded tuning table's entry for
- * (key_type, with_payload, n) if there is one, else the process-wide policy. */
+ * (key_type, with_payload, n) if there is one, else the process-wide policy.
+ * With a table loaded, the recursion also picks the parameters of every global
+ * node (max_buckets, target_child, bins_per_bucket, max_bins,
+ * samples_per_bucket, max_samples, chunk_keys) from the entry whose size class
+ * holds the node's length, so the segments of a batch and the nodes of deeper
+ * levels each use the entry tuned for their own size; the call's entry gives
+ * the rest (lds_cap, tau, seed, model, scatter_tile). */
 int pcf_policy_for(int key_type, size_t n, int with_payload, pcf_policy *out);
 
 /*
  * Autotuner: on the current device, for four size classes ([0, 2^18),
- * [2^18, 2^22), [2^22, 2^25), [2^25, 2^32) keys, timed at 2^16, 2^20, 2^23
- * and 2^26 keys), times candidate policies (max_buckets, samples_per_bucket,
- * bins_per_bucket, chunk_keys, target_child; coordinate descent from the
+ * [2^18, 2^22), [2^22, 2^25), [2^25, 2^32) keys; the first two timed on a
+ * segmented batch of 2^25 keys in segments of floor(2^U[10, 18]) and
+ * floor(2^U[18, 22]) keys, the others on one array of 2^23 and 2^26 keys),
+ * times candidate policies (max_buckets, samples_per_bucket,
+ * bins_per_bucket, chunk_keys, target_child, scatter_tile; coordinate descent from the
  * process-wide policy, hipEvent-timed, median of repeats, summed over uniform,
  * normal and lognormal synthetic arrays) and writes the winners as JSON to
  * out_json (format "pcfsort-tuning-1").  Takes a few seconds and about

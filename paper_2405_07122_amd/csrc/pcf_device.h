@@ -16,6 +16,7 @@ constexpr int KT_F64 = 0;
 constexpr int KT_U64 = 1;
 
 constexpr int MAX_LEVELS = 16;       // global recursion levels per call
+constexpr int MAX_POL_CLASSES = 4;   // tuning-table size classes for node parameters
 constexpr uint32_t MAX_NB = 2048;    // buckets per global node (gamma + 1)
 constexpr uint32_t MAX_BINS = 16383; // beta per global node (table of beta + 1 u16)
 constexpr uint32_t RADIX_NB = 256;   // buckets of a standard-sort (radix) node
@@ -270,8 +271,23 @@ struct Plan {
   // trace (level 0 only): prefix counts b of node 0
   uint32_t* trace_b;
   PolicyDev pol;
+  // tuning-table classes: a node of len keys with cls_min[i] <= len <= cls_max[i]
+  // takes its node parameters (buckets, bins, samples, chunk) from cls[i]
+  PolicyDev cls[MAX_POL_CLASSES];
+  uint32_t cls_min[MAX_POL_CLASSES], cls_max[MAX_POL_CLASSES];
+  uint32_t ncls;
   uint64_t seed;
 };
+
+// The policy whose node parameters a node of `len` keys takes (the loop is
+// unrolled, so the classes are read at fixed offsets of the kernel argument).
+__device__ __forceinline__ PolicyDev node_pol(const Plan& p, uint32_t len) {
+  PolicyDev q = p.pol;
+#pragma unroll
+  for (int i = 0; i < MAX_POL_CLASSES; ++i)
+    if ((uint32_t)i < p.ncls && len >= p.cls_min[i] && len <= p.cls_max[i]) q = p.cls[i];
+  return q;
+}
 
 // Parameters of a node of `len` keys (gamma + 1 = nb buckets, beta bins,
 // alpha samples, failure threshold delta; Sec. 3.3 and the policy).

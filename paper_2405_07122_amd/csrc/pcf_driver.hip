@@ -44,6 +44,7 @@ static pcf_policy g_pol = {
     /*tau*/ 100,
     /*seed*/ 0x5eed,
     /*model*/ 0,
+    /*scatter_tile*/ 0,
 };
 
 pcf_policy current_policy() {
@@ -52,8 +53,9 @@ pcf_policy current_policy() {
 }
 
 // Tuned policies per size class (pcf_load_tuning); sizes no entry covers use
-// g_pol.
+// g_pol.  The version changes with every install (graph cache key).
 static std::vector<TuneEntry> g_table;
+static uint64_t g_table_version = 0;
 
 pcf_policy policy_for(int key_type, size_t n, int has_pay) {
   std::lock_guard<std::mutex> g(g_pol_mu);
@@ -66,6 +68,40 @@ pcf_policy policy_for(int key_type, size_t n, int has_pay) {
 void install_table(const std::vector<TuneEntry>& t) {
   std::lock_guard<std::mutex> g(g_pol_mu);
   g_table = t;
+  ++g_table_version;
+}
+
+// The policies of one call: the call's own (by its total size) and the table's
+// classes of its kind, from which every global node takes its node parameters
+// by its length.  `cover` bounds what any node can use (most buckets, bins and
+// samples, fewest keys per chunk): the workspace layout is sized from it.
+struct CallPolicy {
+  pcf_policy pol, cover;
+  std::vector<TuneEntry> cls;
+  uint64_t version = 0;
+};
+
+static CallPolicy call_policy(int key_type, size_t n, int has_pay, const pcf_policy* override_pol) {
+  CallPolicy c;
+  c.pol = override_pol ? *override_pol : policy_for(key_type, n, has_pay);
+  if (!override_pol) {
+    std::lock_guard<std::mutex> g(g_pol_mu);
+    for (const TuneEntry& e : g_table)
+      if (e.key_type == key_type && e.with_payload == (has_pay ? 1 : 0) &&
+          c.cls.size() < (size_t)MAX_POL_CLASSES)
+        c.cls.push_back(e);
+    c.version = g_table_version;
+  }
+  c.cover = c.pol;
+  for (const TuneEntry& e : c.cls) {
+    c.cover.max_buckets = std::max(c.cover.max_buckets, e.pol.max_buckets);
+    c.cover.max_bins = std::max(c.cover.max_bins, e.pol.max_bins);
+    c.cover.bins_per_bucket = std::max(c.cover.bins_per_bucket, e.pol.bins_per_bucket);
+    c.cover.max_samples = std::max(c.cover.max_samples, e.pol.max_samples);
+    c.cover.target_child = std::min(c.cover.target_child, e.pol.target_child);
+    c.cover.chunk_keys = std::min(c.cover.chunk_keys, e.pol.chunk_keys);
+  }
+  return c;
 }
 
 int check_policy(const pcf_policy& p) {
@@ -78,6 +114,9 @@ int check_policy(const pcf_policy& p) {
   if (p.chunk_keys < 1024 || p.lds_cap < 2048 || p.lds_cap > 8192) return PCF_ERR_INVALID_ARGUMENT;
   if (p.tau < 16 || p.tau > 1024) return PCF_ERR_INVALID_ARGUMENT;
   if (p.model > 1) return PCF_ERR_INVALID_ARGUMENT;
+  if (p.scatter_tile != 0 && p.scatter_tile != 1024 && p.scatter_tile != 2048 &&
+      p.scatter_tile != 4096 && p.scatter_tile != 8192)
+    return PCF_ERR_INVALID_ARGUMENT;
   return PCF_OK;
 }
 
@@ -366,8 +405,9 @@ static int ctl_readback_slot(Ctl** pin, hipEvent_t* ev) {
 // captured into a graph), otherwise it ends like any call: deferred profile
 // marks with a status word, a wait for the outcome without one.
 template <int KT, int PAY>
-static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
+static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const CallPolicy& cp,
                      int fixed_levels, bool capture) {
+  const pcf_policy& pol = cp.pol;
   hipStream_t st = a.stream;
   const int cus = device_cus();
   if (cus <= 0) return PCF_ERR_UNSUPPORTED;
@@ -397,7 +437,7 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   }
   p.mmr = reinterpret_cast<MinMax*>(ws + lay.mmr);
   p.sbuf0 = (a.nseg == 1 && !a.trace) ? reinterpret_cast<uint64_t*>(ws + lay.sbuf0) : nullptr;
-  p.sbuf0_cap = pol.max_samples;
+  p.sbuf0_cap = cp.cover.max_samples;
   p.cap_nodes = lay.cap_nodes;
   p.cap_units = lay.cap_units;
   p.cap_aux = lay.cap_aux;
@@ -405,22 +445,25 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   p.cap_cm = lay.cap_cm;
   p.trace_b = a.trace ? reinterpret_cast<uint32_t*>(ws + lay.trace_b) : nullptr;
   // scatter work per level: enough units to give every workgroup a few
-  const uint32_t bins_lds = std::max<uint32_t>(pol.max_bins, a.trace ? a.trace_beta : 0u);
+  const uint32_t bins_lds = std::max<uint32_t>(cp.cover.max_bins, a.trace ? a.trace_beta : 0u);
   // keys only: the LDS-atomic scatter; with a payload: the stable one
   int sc_ts;
   uint32_t sc_lds;
   if (PAY) {
-    sc_ts = SC_TS_PAY;
+    // 2048-key tiles by default (two 512-thread workgroups per CU); the
+    // policy may ask for 1024
+    sc_ts = pol.scatter_tile == 1024 ? 1024 : SC_TS_PAY;
     sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY, (int)pol.model).total;
     if (sc_lds > 160 * 1024 - 1024) {  // many buckets: halve the tile
       sc_ts /= 2;
       sc_lds = scatter_lds(bins_lds, lay.nbmax, SC_NT / 64, sc_ts, PAY, (int)pol.model).total;
     }
   } else {
-    // 8192-key tiles, 1024 threads, one workgroup per CU: the same scatter
-    // time as two 512-thread workgroups with 4096-key tiles, half the
-    // bucket-edge lines, and longer work units for the count and fit
-    sc_ts = 8192;
+    // 8192-key tiles, 1024 threads, one workgroup per CU by default: the
+    // same scatter time as two 512-thread workgroups with 4096-key tiles,
+    // half the bucket-edge lines, and longer work units for the count and
+    // fit; the policy may ask for 4096
+    sc_ts = pol.scatter_tile == 4096 ? 4096 : 8192;
     sc_lds = scatter_keys_lds(bins_lds, lay.nbmax, sc_ts, (int)pol.model).total;
     if (sc_lds > 160 * 1024 - 1024) {
       sc_ts = 4096;
@@ -456,6 +499,25 @@ static int run_typed(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     pd.prof = (g_prof_on && !a.no_prof) ? 1u : 0u;
   }
   p.pol = pd;
+  // the table's classes: node parameters by node length (the same floor on
+  // keys per chunk as the call's, so a level never has more units than the
+  // layout holds)
+  p.ncls = 0;
+  for (const TuneEntry& e : cp.cls) {
+    if (e.min_n > 0xffffffffull) continue;
+    PolicyDev q = pd;
+    q.max_buckets = e.pol.max_buckets;
+    q.target_child = e.pol.target_child;
+    q.bins_per_bucket = e.pol.bins_per_bucket;
+    q.max_bins = e.pol.max_bins;
+    q.samples_per_bucket = e.pol.samples_per_bucket;
+    q.max_samples = e.pol.max_samples;
+    q.chunk_keys = (uint32_t)std::max<uint64_t>(e.pol.chunk_keys, (a.n + 8ull * g_sc - 1) / (8ull * g_sc));
+    p.cls[p.ncls] = q;
+    p.cls_min[p.ncls] = (uint32_t)e.min_n;
+    p.cls_max[p.ncls] = (uint32_t)std::min<uint64_t>(e.max_n - 1, 0xffffffffull);
+    ++p.ncls;
+  }
   p.seed = (uint64_t)pol.seed;
   p.nlev = fixed_levels > 0 ? (uint32_t)fixed_levels : (a.trace ? 1u : (uint32_t)(MAX_LEVELS - 1));
 
@@ -721,13 +783,13 @@ static int set_attrs() {
   return PCF_OK;
 }
 
-static int dispatch(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
+static int dispatch(const SortArgs& a, const Layout& lay, char* ws, const CallPolicy& cp,
                     int has_pay, int fixed_levels, bool capture = false) {
   if (a.key_type == PCF_KEY_F64)
-    return has_pay ? run_typed<KT_F64, 1>(a, lay, ws, pol, fixed_levels, capture)
-                   : run_typed<KT_F64, 0>(a, lay, ws, pol, fixed_levels, capture);
-  return has_pay ? run_typed<KT_U64, 1>(a, lay, ws, pol, fixed_levels, capture)
-                 : run_typed<KT_U64, 0>(a, lay, ws, pol, fixed_levels, capture);
+    return has_pay ? run_typed<KT_F64, 1>(a, lay, ws, cp, fixed_levels, capture)
+                   : run_typed<KT_F64, 0>(a, lay, ws, cp, fixed_levels, capture);
+  return has_pay ? run_typed<KT_U64, 1>(a, lay, ws, cp, fixed_levels, capture)
+                 : run_typed<KT_U64, 0>(a, lay, ws, cp, fixed_levels, capture);
 }
 
 // ---- graph replay of segmented sorts ----------------------------------------
@@ -746,6 +808,7 @@ struct GraphKey {
   void* ws;
   int32_t* dst;
   pcf_policy pol;
+  uint64_t table_version;  // the tuning table the node parameters came from
 };
 
 struct GraphEntry {
@@ -772,8 +835,9 @@ static bool use_graph(const SortArgs& a) {
   return !g_prof_on;  // profiling records events per launch: eager path
 }
 
-static int run_graph(const SortArgs& a, const Layout& lay, char* ws, const pcf_policy& pol,
+static int run_graph(const SortArgs& a, const Layout& lay, char* ws, const CallPolicy& cp,
                      int has_pay) {
+  const pcf_policy& pol = cp.pol;
   GraphKey k;
   std::memset(&k, 0, sizeof(k));  // padding takes part in the comparison
   PCF_HIP(hipGetDevice(&k.dev));
@@ -790,6 +854,7 @@ static int run_graph(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
   k.ws = ws;
   k.dst = a.d_status;
   k.pol = pol;
+  k.table_version = cp.cls.empty() ? 0 : cp.version;
   std::lock_guard<std::mutex> g(g_graph_mu);
   GraphEntry* e = nullptr;
   for (auto& x : g_graphs)
@@ -800,7 +865,7 @@ static int run_graph(const SortArgs& a, const Layout& lay, char* ws, const pcf_p
     PCF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     SortArgs b = a;
     b.stream = cs;
-    const int rc = dispatch(b, lay, ws, pol, has_pay, chain_levels(a.n, pol.lds_cap), true);
+    const int rc = dispatch(b, lay, ws, cp, has_pay, chain_levels(a.n, pol.lds_cap), true);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &gr);
     if (rc != PCF_OK) {
@@ -866,8 +931,8 @@ int graph_clear() {
 }
 
 size_t workspace_for(int key_type, size_t n, int has_pay, uint32_t nseg, int int_keys) {
-  return make_layout(n, has_pay, nseg ? nseg : 1, policy_for(key_type, n, has_pay), int_keys, 0, 0)
-      .total;
+  const CallPolicy cp = call_policy(key_type, n, has_pay, nullptr);
+  return make_layout(n, has_pay, nseg ? nseg : 1, cp.cover, int_keys, 0, 0).total;
 }
 
 int run_sort(const SortArgs& a) {
@@ -886,10 +951,11 @@ int run_sort(const SortArgs& a) {
   const int has_pay = a.vals_out != nullptr;
   if (has_pay && !a.iota && !a.vals_in) return PCF_ERR_INVALID_ARGUMENT;
   if (!has_pay && !a.keys_out) return PCF_ERR_INVALID_ARGUMENT;
-  const pcf_policy pol = a.pol_override ? *a.pol_override : policy_for(a.key_type, a.n, has_pay);
+  const CallPolicy cp = call_policy(a.key_type, a.n, has_pay, a.pol_override);
+  const pcf_policy& pol = cp.pol;
   int r = set_attrs();
   if (r != PCF_OK) return r;
-  const Layout lay = make_layout(a.n, has_pay, a.nseg, pol, a.keys_out == nullptr,
+  const Layout lay = make_layout(a.n, has_pay, a.nseg, cp.cover, a.keys_out == nullptr,
                                  a.trace ? a.trace_nb : 0, a.trace ? a.trace_beta : 0);
   char* ws = reinterpret_cast<char*>(a.ws);
   bool own = false;
@@ -901,13 +967,13 @@ int run_sort(const SortArgs& a) {
   }
   int rc;
   if (!own && use_graph(a))
-    rc = run_graph(a, lay, ws, pol, has_pay);
+    rc = run_graph(a, lay, ws, cp, has_pay);
   else if (a.d_status && !a.trace)
     // data errors reach the status word, so nothing needs the host: the
     // fixed chain is enqueued and the call returns (a caller may capture it)
-    rc = dispatch(a, lay, ws, pol, has_pay, chain_levels(a.n, pol.lds_cap));
+    rc = dispatch(a, lay, ws, cp, has_pay, chain_levels(a.n, pol.lds_cap));
   else
-    rc = dispatch(a, lay, ws, pol, has_pay, 0);
+    rc = dispatch(a, lay, ws, cp, has_pay, 0);
   if (own) {
     hipError_t e = hipFreeAsync(ws, a.stream);
     if (e != hipSuccess && rc == PCF_OK) rc = hip_fail(e);
@@ -969,9 +1035,9 @@ int pcf_last_hip_error(void) { return g_last_hip_error; }
 const char* pcf_version(void) { return "pcfsort 0.1 (gfx950)"; }
 
 size_t pcf_workspace_bytes(int key_type, size_t n, int with_payload, uint32_t num_segments) {
-  const pcf_policy pol = policy_for(key_type, n, with_payload);
+  const CallPolicy cp = call_policy(key_type, n, with_payload, nullptr);
   // argsort may need internal keys: include them
-  return make_layout(n, with_payload, num_segments ? num_segments : 1, pol, with_payload, 0, 0)
+  return make_layout(n, with_payload, num_segments ? num_segments : 1, cp.cover, with_payload, 0, 0)
       .total;
 }
 

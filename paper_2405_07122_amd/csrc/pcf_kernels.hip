@@ -110,10 +110,12 @@ __global__ __launch_bounds__(ROOT_NT) void k_roots(Plan p, RootArgs a) {
         beta = a.fixed_beta;
         alpha = a.fixed_alpha;
         delta = len + 1;
+        nch = (len + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
       } else {
-        node_params(len, p.pol.model ? NK_SPLINE : NK_PCF, p.pol, nb, beta, alpha, delta);
+        const PolicyDev np = node_pol(p, len);
+        node_params(len, p.pol.model ? NK_SPLINE : NK_PCF, np, nb, beta, alpha, delta);
+        nch = (len + np.chunk_keys - 1) / np.chunk_keys;
       }
-      nch = (len + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
     }
     uint32_t tot;
     const uint32_t o_node = block_excl_scan<ROOT_NT>(glob ? 1u : 0u, red, tot);
@@ -761,9 +763,10 @@ __global__ __launch_bounds__(NT) void k_classify(Plan p, int L, LevelIO io) {
         }
         if (kq >= BC_GLB_PCF && has_next) {
           const uint32_t sz = st[q + 1] - st[q];
-          node_params(sz, kq == BC_GLB_RADIX ? NK_RADIX : (p.pol.model ? NK_SPLINE : NK_PCF), p.pol, cnb[k], cbeta[k],
-                      calpha[k], cdelta[k]);
-          cnch[k] = (sz + p.pol.chunk_keys - 1) / p.pol.chunk_keys;
+          const PolicyDev np = node_pol(p, sz);
+          node_params(sz, kq == BC_GLB_RADIX ? NK_RADIX : (p.pol.model ? NK_SPLINE : NK_PCF), np,
+                      cnb[k], cbeta[k], calpha[k], cdelta[k]);
+          cnch[k] = (sz + np.chunk_keys - 1) / np.chunk_keys;
           ++n_node;
           n_unit += cnch[k];
           n_tab += kq == BC_GLB_PCF ? cbeta[k] + 1 : 0u;

@@ -59,15 +59,20 @@ void make_keys(int kt, int dist, uint64_t seed, std::vector<uint64_t>& out) {
   }
 }
 
+// A size class and what it is timed on: one array of rep_n keys, or (seg_lo <
+// seg_hi) a segmented batch of rep_n keys in segments of floor(2^U[seg_lo,
+// seg_hi]) keys, so that a class of small arrays is timed by its throughput
+// (the batched use) rather than by the launch latency of one small sort.
 struct Class {
   uint64_t min_n, max_n, rep_n;
+  double seg_lo, seg_hi;
 };
 
 const Class kClasses[] = {
-    {0, 1ull << 18, 1ull << 16},
-    {1ull << 18, 1ull << 22, 1ull << 20},
-    {1ull << 22, 1ull << 25, 1ull << 23},
-    {1ull << 25, 1ull << 32, 1ull << 26},
+    {0, 1ull << 18, 1ull << 25, 10.0, 18.0},
+    {1ull << 18, 1ull << 22, 1ull << 25, 18.0, 22.0},
+    {1ull << 22, 1ull << 25, 1ull << 23, 0.0, 0.0},
+    {1ull << 25, 1ull << 32, 1ull << 26, 0.0, 0.0},
 };
 
 struct Bench {
@@ -79,8 +84,11 @@ struct Bench {
   size_t ws_bytes = 0;
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  uint64_t* offs = nullptr;  // device CSR offsets of the current class's batch (or none)
+  uint32_t nseg = 1;
 
   ~Bench() {
+    if (offs) (void)hipFree(offs);
     for (void* k : keys)
       if (k) (void)hipFree(k);
     if (out) (void)hipFree(out);
@@ -99,7 +107,9 @@ struct Bench {
     a.keys_out = out;
     a.vals_out = pay ? idx : nullptr;
     a.iota = pay ? 1 : 0;
-    a.nseg = 1;
+    a.nseg = nseg;
+    a.offsets = nseg > 1 ? offs : nullptr;
+    a.no_graph = 1;
     a.n = n;
     a.ws = ws;
     a.ws_bytes = ws_bytes;
@@ -116,7 +126,7 @@ struct Bench {
   // median over `reps` of the summed time over the three distributions
   double score(const pcf_policy& pol, size_t n, int reps) {
     if (pcf::check_policy(pol) != PCF_OK) return -1.0;
-    if (pcf::make_layout(n, pay, 1, pol, 0, 0, 0).total > ws_bytes) return -1.0;
+    if (pcf::make_layout(n, pay, nseg, pol, 0, 0, 0).total > ws_bytes) return -1.0;
     std::vector<double> v;
     for (int r = 0; r < reps; ++r) {
       double t = 0;
@@ -254,16 +264,16 @@ struct JParser {
   }
 };
 
-constexpr int kNumFields = 11;
+constexpr int kNumFields = 12;
 const char* kFields[kNumFields] = {"max_buckets", "target_child", "bins_per_bucket", "max_bins",
                                    "samples_per_bucket", "max_samples", "chunk_keys", "lds_cap",
-                                   "tau", "seed", "model"};
+                                   "tau", "seed", "model", "scatter_tile"};
 
 uint32_t* field(pcf_policy& p, int i) {
   uint32_t* f[kNumFields] = {&p.max_buckets, &p.target_child,       &p.bins_per_bucket,
                              &p.max_bins,    &p.samples_per_bucket, &p.max_samples,
                              &p.chunk_keys,  &p.lds_cap,            &p.tau,
-                             &p.seed,        &p.model};
+                             &p.seed,        &p.model,              &p.scatter_tile};
   return f[i];
 }
 
@@ -312,6 +322,7 @@ int pcf_autotune(int key_type, int with_payload, const char* out_json) {
       {2, {8, 16, 32}},              // bins_per_bucket
       {6, {8192, 16384, 32768}},     // chunk_keys
       {1, {1024, 2048, 4096, 8192}}, // target_child
+      {11, pay ? std::vector<uint32_t>{1024, 2048} : std::vector<uint32_t>{4096, 8192}},  // scatter_tile
   };
   // the workspace must hold every candidate's layout at the largest size
   const pcf_policy base = pcf::current_policy();
@@ -327,13 +338,32 @@ int pcf_autotune(int key_type, int with_payload, const char* out_json) {
             c.bins_per_bucket = bp;
             c.chunk_keys = ck;
             c.target_child = tc;
-            b.ws_bytes = std::max(b.ws_bytes, pcf::make_layout(nmax, pay, 1, c, 0, 0, 0).total);
+            b.ws_bytes = std::max(b.ws_bytes, pcf::make_layout(nmax, pay, 4096, c, 0, 0, 0).total);
           }
   if (hipMalloc(&b.ws, b.ws_bytes) != hipSuccess) return PCF_ERR_OUT_OF_MEMORY;
 
   std::vector<TuneEntry> table;
   for (const Class& c : kClasses) {
     const size_t n = c.rep_n;
+    // the class's batch: segment sizes from a fixed SplitMix64 stream
+    b.nseg = 1;
+    if (c.seg_lo < c.seg_hi) {
+      std::vector<uint64_t> off(1, 0);
+      uint64_t rs = 0x5e65ull + (uint64_t)c.min_n;
+      while (off.back() < n && off.size() < 4096) {
+        const double u = (double)(sm64(rs) >> 11) * 0x1.0p-53;
+        const uint64_t len = (uint64_t)std::floor(std::exp2(c.seg_lo + u * (c.seg_hi - c.seg_lo)));
+        off.push_back(std::min<uint64_t>(n, off.back() + std::max<uint64_t>(len, 1)));
+      }
+      off.back() = n;
+      if (b.offs) (void)hipFree(b.offs);
+      b.offs = nullptr;
+      if (hipMalloc(reinterpret_cast<void**>(&b.offs), off.size() * 8) != hipSuccess)
+        return PCF_ERR_OUT_OF_MEMORY;
+      if (hipMemcpy(b.offs, off.data(), off.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return PCF_ERR_HIP;
+      b.nseg = (uint32_t)(off.size() - 1);
+    }
     const int reps = n >= (1u << 23) ? 3 : 5;
     pcf_policy best = base;
     (void)b.score(best, n, 1);  // warm-up

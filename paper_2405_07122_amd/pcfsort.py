@@ -56,7 +56,7 @@ class PcfError(RuntimeError):
 class Policy(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "max_buckets", "target_child", "bins_per_bucket", "max_bins", "samples_per_bucket",
-        "max_samples", "chunk_keys", "lds_cap", "tau", "seed", "model")]
+        "max_samples", "chunk_keys", "lds_cap", "tau", "seed", "model", "scatter_tile")]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
