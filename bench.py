@@ -12,7 +12,8 @@ the timed region; `cpu_baseline` is the CPU oracle on the bytes of one timed
 sort, with std::sort beside it.  Extra legs: the enqueue-only form of the
 same calls, argsort of the six arrays, the spline model, App. D's four-way
 runtime profile on normal and point-mass inputs, the serving trace, the
-segmented batch, the skewed uint64 workload at 2e8 keys, and (with --lfail)
+segmented batch, the skewed uint64 workload at 2e8 keys, the in-place
+variant, and (with --lfail)
 the bucketing-failure experiment.
 """
 from __future__ import annotations
@@ -453,6 +454,44 @@ def u64_leg(P, n: int, reps: int = 3):
             "reps": reps}
 
 
+def inplace_leg(P, dev: dict, reps: int = 3):
+    """The in-place variant on the 1e8-key arrays: keys sorted within their own
+    array (a fresh copy per run, made outside the timed call), checked against
+    torch's sort; its workspace beside the out-of-place call's."""
+    import numpy as np
+    import torch
+    res = {}
+    n = next(iter(dev.values())).numel()
+    ws = torch.empty(P.inplace_workspace_bytes(P.KEY_F64, n), dtype=torch.uint8, device="cuda")
+    work = torch.empty(n, dtype=torch.float64, device="cuda")
+    for d in ("uniform", "lognormal"):
+        if d not in dev:
+            continue
+        ts = []
+        for r in range(reps + 1):
+            work.copy_(dev[d])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.pcf_sort_inplace(work, ws=ws)  # waits for its outcome
+            if r:
+                ts.append(time.perf_counter() - t0)
+        ref, _ = torch.sort(dev[d])
+        if not torch.equal(work, ref):
+            raise RuntimeError(f"in-place {d}: output differs from torch.sort")
+        del ref
+        res[d] = {"median_ms": float(np.median(ts)) * 1e3, "min_ms": float(min(ts)) * 1e3,
+                  "keys_per_s": n / float(np.median(ts))}
+    wsi = P.inplace_workspace_bytes(P.KEY_F64, n)
+    wso = P.workspace_bytes(P.KEY_F64, n)
+    del ws, work
+    torch.cuda.empty_cache()
+    return {"workload": f"pcf_sort_inplace n={n} fp64 keys", "n": n, "runs": res,
+            "workspace_bytes": wsi, "workspace_bytes_per_key": wsi / n,
+            "out_of_place_workspace_bytes": wso, "out_of_place_bytes_per_key": wso / n,
+            "device_bytes_per_key_in_place": 8 + wsi / n,
+            "device_bytes_per_key_out_of_place_in_eq_out": 8 + wso / n}
+
+
 def lfail_leg(P, n: int = 1_000_000, reps: int = 100):
     """The bucketing-failure experiment of Sec. 4.2 (Fig. 3): alpha, beta,
     gamma, delta = floor(n^{a,b,c,d}); six heatmaps over two of the exponents
@@ -522,6 +561,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-argsort", action="store_true", help="skip the argsort leg")
     ap.add_argument("--no-u64", action="store_true", help="skip the uint64 leg")
+    ap.add_argument("--no-inplace", action="store_true", help="skip the in-place leg")
     ap.add_argument("--u64-n", type=int, default=200_000_000)
     ap.add_argument("--no-batched", action="store_true", help="skip the segmented leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
@@ -670,6 +710,10 @@ def main():
 
     if not args.no_stages:
         extra["stages"] = stages_leg(pcfsort, args.stages_n)
+
+    if not args.no_inplace:
+        extra["inplace"] = inplace_leg(pcfsort, dev)
+        log(f"in place: {extra['inplace']['runs']}")
 
     if not args.no_served:
         extra["served"] = served_leg(pcfsort, dev, [float(r) for r in args.served_rates.split(",")],

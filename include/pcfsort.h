@@ -114,6 +114,24 @@ int pcf_sort_f64_static(const double *d_in, double *d_out, size_t n, int32_t *d_
                         void *stream);
 
 /*
+ * In-place variant (the in-place forms of sample sort that Sec. 5 points to):
+ * sorts the n keys of d_keys within that array.  A node larger than a fixed
+ * staging capacity (2^24 keys) is bucketed in place (the model's 256 buckets,
+ * eight rounds of a two-way in-place partition on the bits of the bucket id);
+ * buckets are then sorted through a staging buffer of at most that many keys
+ * by the segmented sort, and larger ones are bucketed in place again (with the
+ * standard sort's radix digits once a bucket has failed, |c_j| >= delta).
+ * Keys only: the swaps are not stable.  Workspace: pcf_inplace_workspace_bytes
+ * (the staging buffer and its sort workspace, plus 1/64 of the key bytes for
+ * marks and block counts), or d_ws = NULL to allocate it stream-ordered.
+ * Waits for `stream` and returns the outcome (PCF_ERR_INVALID_KEY for an
+ * invalid fp64 key).  n < 2^32.
+ */
+size_t pcf_inplace_workspace_bytes(int key_type, size_t n);
+int pcf_sort_inplace(int key_type, void *d_keys, size_t n, void *d_ws, size_t ws_bytes,
+                     void *stream);
+
+/*
  * Argsort (Algorithm 1 with each key carrying its input position).
  * d_idx_out[k] receives the input position of the k-th smallest key; ties
  * are broken by ascending position.  d_keys_out (nullable) receives the

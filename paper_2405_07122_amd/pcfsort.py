@@ -31,7 +31,8 @@ KEY_U64 = 1
 
 EXPORTS = [
     "pcf_status_string", "pcf_last_hip_error", "pcf_version", "pcf_workspace_bytes",
-    "pcf_sort_f64", "pcf_sort_u64", "pcf_sort_f64_static", "pcf_argsort", "pcf_sort_segmented", "pcf_level_trace",
+    "pcf_sort_f64", "pcf_sort_u64", "pcf_sort_f64_static", "pcf_sort_inplace",
+    "pcf_inplace_workspace_bytes", "pcf_argsort", "pcf_sort_segmented", "pcf_level_trace",
     "pcf_get_policy", "pcf_set_policy", "pcf_autotune", "pcf_load_tuning",
     "pcf_serve_create", "pcf_serve_submit", "pcf_serve_submit_after", "pcf_serve_poll", "pcf_serve_wait",
     "pcf_serve_release", "pcf_serve_get_stats", "pcf_serve_destroy",
@@ -116,6 +117,8 @@ def load(path: str = LIB_PATH):
         "pcf_sort_f64": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
         "pcf_sort_u64": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
         "pcf_sort_f64_static": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
+        "pcf_sort_inplace": (_INT, [_INT, _VP, _SZ, _VP, _SZ, _VP]),
+        "pcf_inplace_workspace_bytes": (_SZ, [_INT, _SZ]),
         "pcf_argsort": (_INT, [_INT, _VP, _VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
         "pcf_sort_segmented": (_INT, [_INT, _VP, _VP, _VP, _VP, _VP, _U32, _SZ, _VP, _SZ, _VP,
                                       _VP]),
@@ -240,6 +243,22 @@ def pcf_sort_f64_static(keys: torch.Tensor, d_status: torch.Tensor, out: torch.T
     _check(lib.pcf_sort_f64_static(_ptr(keys), _ptr(out), keys.numel(), _ptr(d_status),
                                    _stream(stream)), "pcf_sort_f64_static")
     return out
+
+
+def inplace_workspace_bytes(key_type: int, n: int) -> int:
+    return int(load().pcf_inplace_workspace_bytes(key_type, n))
+
+
+def pcf_sort_inplace(keys: torch.Tensor, ws=None, stream=None) -> torch.Tensor:
+    """Sorts `keys` (float64 or 64-bit integer read as unsigned) within its own
+    memory; returns `keys`.  Waits for the stream."""
+    lib = load()
+    kt = _key_type(keys)
+    _need_cuda(keys)
+    wp, wb = _ws_args(ws)
+    _check(lib.pcf_sort_inplace(kt, _ptr(keys), keys.numel(), wp, wb, _stream(stream)),
+           "pcf_sort_inplace")
+    return keys
 
 
 def sort(keys: torch.Tensor, out=None, ws=None, d_status=None, stream=None) -> torch.Tensor:
