@@ -310,7 +310,9 @@ int pcf_policy_for(int key_type, size_t n, int with_payload, pcf_policy *out);
  * bins_per_bucket, chunk_keys, target_child, scatter_tile; coordinate descent from the
  * process-wide policy, hipEvent-timed, median of repeats, summed over uniform,
  * normal and lognormal synthetic arrays) and writes the winners as JSON to
- * out_json (format "pcfsort-tuning-1").  Takes a few seconds and about
+ * out_json (format "pcfsort-tuning-1"; an entry's rep_n is the number of keys
+ * it was timed on, for the two small classes the batch's total, which lies
+ * outside the class's own [min_n, max_n)).  Takes a few seconds and about
  * 4.5 GB of device memory; does not change the active policy.
  * pcf_load_tuning reads such a file, validates every entry (policy limits as
  * pcf_set_policy, no overlapping classes of one kind) and installs it as the

@@ -33,7 +33,10 @@ def test_autotune_roundtrip(P, oracle, tmp_path):
         assert e["ms_per_sort"] > 0 and e["policy"]["max_buckets"] in (64, 128, 256, 512)
     P.pcf_load_tuning(str(out))
     for e in t["entries"]:
-        assert P.policy_for(P.KEY_F64, e["rep_n"])["max_buckets"] == e["policy"]["max_buckets"]
+        # rep_n is what the class was timed on (for the small classes a
+        # segmented batch larger than the class); look the class up by its range
+        for n in (max(e["min_n"], 1), e["max_n"] - 1):
+            assert P.policy_for(P.KEY_F64, n) == e["policy"], (n, e)
     for n, dist in [(300_001, "lognormal"), (5_000_000, "mix8"), (40_000_000, "normal")]:
         x = datagen.f64(dist, n, 77)
         d = to_dev(x)
