@@ -1181,238 +1181,216 @@ __global__ __launch_bounds__(NT, (TS / NT >= 16 ? 2 : 4)) void k_scatter_keys(Pl
   uint32_t tab_node = 0xffffffffu;  // node whose table the LDS holds
   uint64_t* ok_ = reinterpret_cast<uint64_t*>(p.out_keys);
 
-  // Work of a workgroup: ranges of the level's count units (8 * per ranges
-  // of about nu / (8 * per) units, dealt XCD-contiguously: neighbouring
-  // ranges, which share lines at bucket edges, meet in one XCD's L2), split
-  // where the node changes.  Consecutive chunks of a node are consecutive
-  // keys and, in every bucket, consecutive output positions, so such a run of
-  // units is scattered as one stretch of keys: each bucket's output run
-  // continues across chunk boundaries and only the stretch's two ends leave
-  // partly written lines to share with other workgroups.
-  const uint32_t per = (gridDim.x + 7) / 8, nr = 8 * per;
-  for (uint32_t v = blockIdx.x; v < nr; v += gridDim.x) {
-    const uint32_t r = xcd_unit(v, per);
-    const uint32_t ue = (uint32_t)(((uint64_t)nu * (r + 1)) / nr);
-    for (uint32_t u = (uint32_t)(((uint64_t)nu * r) / nr); u < ue;) {
-      const Unit un = p.units[s][u];
-      uint32_t u2 = u + 1;
-      while (u2 < ue && p.units[s][u2].node == un.node) ++u2;
-      const uint32_t j0 = un.chunk, j1 = un.chunk + (u2 - u);  // chunks [j0, j1) of the node
-      u = u2;
-      const Node& nd = p.nodes[s][un.node];
-      uint32_t cb, ce, cx;
-      chunk_range(nd, j0, cb, cx);
-      chunk_range(nd, j1 - 1, cx, ce);
-      const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
-      if (nd.state == NS_DONE) {
-        // single-valued node: already in order; move it to the output if needed
-        uint64_t* o = ok_ + nd.off;
-        if ((const void*)o != nd.src)
-          for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) gst(o)[i] = gld(src)[i];
-        continue;
-      }
-      const uint32_t nb = nd.nb, C = nd.nchunks;
-      if (nd.kind != NK_RADIX && un.node != tab_node) {
-        tab_node = un.node;
-        const uint16_t* tg = p.table[s] + nd.table_off;
-        if (tab8)
-          for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = (unsigned char)tg[i];
-        else
-          for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT)
-            reinterpret_cast<uint16_t*>(tab)[i] = tg[i];
-      }
-      const uint32_t* bs = p.bstart[s] + nd.aux_off;
-      const int32_t* cm = p.cmap[s] + nd.aux_off;
-      const uint32_t* col = p.cm[s] + nd.cm_off;
-      bool glb = false;
-      for (uint32_t q = threadIdx.x; q < nb; q += NT) {
-        runoff[q] = bs[q] + col[(uint64_t)q * C + j0];
-        tcnt[q] = 0u;
-        const bool g = cm[q] >= 0;
-        cmapf[q] = g ? 1 : 0;
-        glb |= g;
-        mmlo[q] = ~0ull;
-        mmhi[q] = 0ull;
-      }
-      const bool any_glb = __syncthreads_or(glb) != 0;
-      const Bucketer<KT> bk = make_bucketer<KT>(nd, tab, tab8);
+  const uint32_t per = (nu + 7) / 8;
+  for (uint32_t v = blockIdx.x; v < 8 * per; v += gridDim.x) {
+    const uint32_t u = xcd_unit(v, per);
+    if (u >= nu) continue;
+    const Unit un = p.units[s][u];
+    const Node& nd = p.nodes[s][un.node];
+    uint32_t cb, ce;
+    chunk_range(nd, un.chunk, cb, ce);
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(nd.src);
+    if (nd.state == NS_DONE) {
+      // single-valued node: already in order; move it to the output if needed
+      uint64_t* o = ok_ + nd.off;
+      if ((const void*)o != nd.src)
+        for (uint32_t i = cb + threadIdx.x; i < ce; i += NT) gst(o)[i] = gld(src)[i];
+      continue;
+    }
+    const uint32_t nb = nd.nb, C = nd.nchunks;
+    if (nd.kind != NK_RADIX && un.node != tab_node) {
+      tab_node = un.node;
+      const uint16_t* tg = p.table[s] + nd.table_off;
+      if (tab8)
+        for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT) tab[i] = (unsigned char)tg[i];
+      else
+        for (uint32_t i = threadIdx.x; i <= nd.beta; i += NT)
+          reinterpret_cast<uint16_t*>(tab)[i] = tg[i];
+    }
+    const uint32_t* bs = p.bstart[s] + nd.aux_off;
+    const int32_t* cm = p.cmap[s] + nd.aux_off;
+    const uint32_t* col = p.cm[s] + nd.cm_off;
+    bool glb = false;
+    for (uint32_t q = threadIdx.x; q < nb; q += NT) {
+      runoff[q] = bs[q] + col[(uint64_t)q * C + un.chunk];
+      tcnt[q] = 0u;
+      const bool g = cm[q] >= 0;
+      cmapf[q] = g ? 1 : 0;
+      glb |= g;
+      mmlo[q] = ~0ull;
+      mmhi[q] = 0ull;
+    }
+    const bool any_glb = __syncthreads_or(glb) != 0;
+    const Bucketer<KT> bk = make_bucketer<KT>(nd, tab, tab8);
 
-      // software pipeline: the next tile's keys are in flight while this one
-      // is ranked, staged and written.  Every tile issues the same vector-memory
-      // instructions (R loads, then R stores, with clamped addresses and no
-      // branch around them), so the wait for the prefetched keys is a fixed
-      // count that leaves the previous tile's stores in flight.  Range-check
-      // failures are collected and reported after the unit.
-      bool bad = false;
-      uint64_t key[R], nkey[R];
-      // the common case: a PCF node with a byte table and an unhalved range,
-      // whose bucket needs none of the general Bucketer's per-key tests (same
-      // arithmetic, same result)
-      const bool fast = KT == KT_F64 && nd.kind == NK_PCF && tab8 && !bk.f.halves;
-      // (chunks of a node are never empty; the clamped addresses below need a
-      // key: an empty chunk skips the tiles and leaves neutral ranges)
-      if (cb < ce) {
+    // software pipeline: the next tile's keys are in flight while this one
+    // is ranked, staged and written.  Every tile issues the same vector-memory
+    // instructions (R loads, then R stores, with clamped addresses and no
+    // branch around them), so the wait for the prefetched keys is a fixed
+    // count that leaves the previous tile's stores in flight.  Range-check
+    // failures are collected and reported after the unit.
+    bool bad = false;
+    uint64_t key[R], nkey[R];
+    // the common case: a PCF node with a byte table and an unhalved range,
+    // whose bucket needs none of the general Bucketer's per-key tests (same
+    // arithmetic, same result)
+    const bool fast = KT == KT_F64 && nd.kind == NK_PCF && tab8 && !bk.f.halves;
+    // (chunks of a node are never empty; the clamped addresses below need a
+    // key: an empty chunk skips the tiles and leaves neutral ranges)
+    if (cb < ce) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = cb + w * PW + r * 64 + l;
+        nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
+      }
+      for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
+        const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) key[r] = nkey[r];
+        const uint32_t t1 = t0 + TS;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint32_t i = cb + w * PW + r * 64 + l;
+          const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
           nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
         }
-        for (uint32_t t0 = cb; t0 < ce; t0 += TS) {
-          const uint32_t tn = (ce - t0 < (uint32_t)TS) ? ce - t0 : (uint32_t)TS;
-#pragma unroll
-          for (int r = 0; r < R; ++r) key[r] = nkey[r];
-          const uint32_t t1 = t0 + TS;
+        // A: bucket of every key (all table reads issued before any atomic),
+        // rank inside the tile's bucket, child ranges
+        uint32_t qq[R];
+        if (fast) {
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            const uint32_t i = t1 + w * PW + r * 64 + l;  // past the chunk: the last key again
-            nkey[r] = __builtin_nontemporal_load(gld(src) + (i < ce ? i : ce - 1));
+            const double pos = KT == KT_F64
+                                   ? (__longlong_as_double((long long)key[r]) - bk.f.lo) * bk.f.s
+                                   : (double)(key[r] - bk.f.lo_bits) * bk.f.s;
+            const uint32_t k = (uint32_t)floor(pos);
+            qq[r] = k < bk.f.beta ? k : bk.f.beta;
           }
-          // A: bucket of every key (all table reads issued before any atomic),
-          // rank inside the tile's bucket, child ranges
-          uint32_t qq[R];
-          if (fast) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const double pos = KT == KT_F64
-                                     ? (__longlong_as_double((long long)key[r]) - bk.f.lo) * bk.f.s
-                                     : (double)(key[r] - bk.f.lo_bits) * bk.f.s;
-              const uint32_t k = (uint32_t)floor(pos);
-              qq[r] = k < bk.f.beta ? k : bk.f.beta;
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const uint32_t i = w * PW + r * 64 + l;
-              const uint32_t q = tab[qq[r]];  // T_i <= gamma < nb
-              qq[r] = i < tn ? q : 0u;
-            }
-          } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const uint32_t i = w * PW + r * 64 + l;
-              uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
-              bad |= q >= nb;  // range check: cannot happen for a consistent model
-              qq[r] = q < nb ? q : nb - 1;
-            }
-          }
-          uint32_t code[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const uint32_t i = w * PW + r * 64 + l;
-            const bool valid = i < tn;
-            const uint32_t q = qq[r];
-            const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
-            const uint64_t act = __ballot(valid);
-            uint32_t rk = 0;
-            if (act == ~0ull && __all(q == q0)) {
-              // the whole wave in one bucket (runs of near-equal keys)
-              uint32_t b0 = 0;
-              if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
-              rk = __builtin_amdgcn_readfirstlane(b0) + l;
-              if (any_glb && cmapf[q0]) {
-                const uint64_t im = img_of<KT>(key[r]);
-                const uint64_t wlo = wave_min_u64(im), whi = wave_max_u64(im);
-                if (l == 0) {
-                  atomicMin(&mmlo[q0], (unsigned long long)wlo);
-                  atomicMax(&mmhi[q0], (unsigned long long)whi);
-                }
-              }
-            } else if (valid) {
-              rk = atomicAdd(&tcnt[q], 1u);
-              if (any_glb && cmapf[q]) {
-                const unsigned long long im = img_of<KT>(key[r]);
-                atomicMin(&mmlo[q], im);
-                atomicMax(&mmhi[q], im);
-              }
-            }
-            code[r] = (q << 16) | rk;
+            const uint32_t q = tab[qq[r]];  // T_i <= gamma < nb
+            qq[r] = i < tn ? q : 0u;
           }
-          __syncthreads();
-          // B (wave 0): tile bucket starts, write bases, next run offsets, counters
-          if (w == 0) {
-            uint32_t carry = 0;
-            for (uint32_t q0 = 0; q0 < nb; q0 += 64) {
-              const uint32_t q = q0 + l;
-              const uint32_t v = q < nb ? tcnt[q] : 0u;
-              const uint32_t x = wave_incl_scan(v);
-              if (q < nb) {
-                const uint32_t st = carry + x - v;
-                const uint32_t ro = runoff[q];
-                tstart[q] = st;
-                wbase[q] = ro - st;
-                runoff[q] = ro + v;
-                tcnt[q] = 0u;
-              }
-              carry += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-            }
-          }
-          __syncthreads();
-          // C: stage keys in bucket order
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) qq[r] = bk.index(key[r]);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const uint32_t i = w * PW + r * 64 + l;
-            if (i < tn) {
-              const uint32_t q = code[r] >> 16;
-              const uint32_t pos = tstart[q] + (code[r] & 0xffffu);
-              if (pos < (uint32_t)TS) {
-                sk[pos] = key[r];
-                sb[pos] = (uint16_t)q;
-              } else {
-                bad = true;
+            uint32_t q = i < tn ? bk.finish2(qq[r], key[r]) : 0u;
+            bad |= q >= nb;  // range check: cannot happen for a consistent model
+            qq[r] = q < nb ? q : nb - 1;
+          }
+        }
+        uint32_t code[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          const bool valid = i < tn;
+          const uint32_t q = qq[r];
+          const uint32_t q0 = __builtin_amdgcn_readfirstlane(q);
+          const uint64_t act = __ballot(valid);
+          uint32_t rk = 0;
+          if (act == ~0ull && __all(q == q0)) {
+            // the whole wave in one bucket (runs of near-equal keys)
+            uint32_t b0 = 0;
+            if (l == 0) b0 = atomicAdd(&tcnt[q0], 64u);
+            rk = __builtin_amdgcn_readfirstlane(b0) + l;
+            if (any_glb && cmapf[q0]) {
+              const uint64_t im = img_of<KT>(key[r]);
+              const uint64_t wlo = wave_min_u64(im), whi = wave_max_u64(im);
+              if (l == 0) {
+                atomicMin(&mmlo[q0], (unsigned long long)wlo);
+                atomicMax(&mmhi[q0], (unsigned long long)whi);
               }
             }
+          } else if (valid) {
+            rk = atomicAdd(&tcnt[q], 1u);
+            if (any_glb && cmapf[q]) {
+              const unsigned long long im = img_of<KT>(key[r]);
+              atomicMin(&mmlo[q], im);
+              atomicMax(&mmhi[q], im);
+            }
           }
-          __syncthreads();
-          // D: write runs (consecutive staged keys of one bucket go to consecutive
-          // addresses); no barrier after it: the next tile's rank phase touches
-          // only tcnt and the min/max, and its bucket-start phase comes after the
-          // next barrier
-          // (per half: the staged ids, then their write bases, then the keys,
-          // each a batch of independent LDS reads).  A lane past the tile's end
-          // repeats the store of the tile's last key: same value, same address.
-          {
-            constexpr int H = R / 2 > 0 ? R / 2 : 1;
+          code[r] = (q << 16) | rk;
+        }
+        __syncthreads();
+        // B (wave 0): tile bucket starts, write bases, next run offsets, counters
+        if (w == 0) {
+          uint32_t carry = 0;
+          for (uint32_t q0 = 0; q0 < nb; q0 += 64) {
+            const uint32_t q = q0 + l;
+            const uint32_t v = q < nb ? tcnt[q] : 0u;
+            const uint32_t x = wave_incl_scan(v);
+            if (q < nb) {
+              const uint32_t st = carry + x - v;
+              const uint32_t ro = runoff[q];
+              tstart[q] = st;
+              wbase[q] = ro - st;
+              runoff[q] = ro + v;
+              tcnt[q] = 0u;
+            }
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+          }
+        }
+        __syncthreads();
+        // C: stage keys in bucket order
 #pragma unroll
-            for (int h = 0; h < R; h += H) {
-              uint32_t qd[H], wb[H], ic[H];
-              uint64_t kd[H];
+        for (int r = 0; r < R; ++r) {
+          const uint32_t i = w * PW + r * 64 + l;
+          if (i < tn) {
+            const uint32_t q = code[r] >> 16;
+            const uint32_t pos = tstart[q] + (code[r] & 0xffffu);
+            if (pos < (uint32_t)TS) {
+              sk[pos] = key[r];
+              sb[pos] = (uint16_t)q;
+            } else {
+              bad = true;
+            }
+          }
+        }
+        __syncthreads();
+        // D: write runs (consecutive staged keys of one bucket go to consecutive
+        // addresses); no barrier after it: the next tile's rank phase touches
+        // only tcnt and the min/max, and its bucket-start phase comes after the
+        // next barrier
+        // (per half: the staged ids, then their write bases, then the keys,
+        // each a batch of independent LDS reads).  A lane past the tile's end
+        // repeats the store of the tile's last key: same value, same address.
+        {
+          constexpr int H = R / 2 > 0 ? R / 2 : 1;
 #pragma unroll
-              for (int r = 0; r < H; ++r) {
-                const uint32_t i = (h + r) * NT + threadIdx.x;
-                ic[r] = i < tn ? i : tn - 1;
-                qd[r] = sb[ic[r]];
-              }
+          for (int h = 0; h < R; h += H) {
+            uint32_t qd[H], wb[H], ic[H];
+            uint64_t kd[H];
 #pragma unroll
-              for (int r = 0; r < H; ++r) wb[r] = wbase[qd[r]];
+            for (int r = 0; r < H; ++r) {
+              const uint32_t i = (h + r) * NT + threadIdx.x;
+              ic[r] = i < tn ? i : tn - 1;
+              qd[r] = sb[ic[r]];
+            }
 #pragma unroll
-              for (int r = 0; r < H; ++r) kd[r] = sk[ic[r]];
+            for (int r = 0; r < H; ++r) wb[r] = wbase[qd[r]];
 #pragma unroll
-              for (int r = 0; r < H; ++r) {
-                const uint32_t rel = wb[r] + ic[r];
-                bad |= rel >= nd.len;
-                gst(dk)[nd.off + (rel < nd.len ? rel : nd.len - 1)] = kd[r];
-              }
+            for (int r = 0; r < H; ++r) kd[r] = sk[ic[r]];
+#pragma unroll
+            for (int r = 0; r < H; ++r) {
+              const uint32_t rel = wb[r] + ic[r];
+              bad |= rel >= nd.len;
+              gst(dk)[nd.off + (rel < nd.len ? rel : nd.len - 1)] = kd[r];
             }
           }
         }
       }
-      if (bad) flag_internal(c);
-      __syncthreads();
-      if (any_glb) {
-        // the stretch's range of every child that is a node of the next level,
-        // in the slot of its first chunk; the slots of the other chunks get the
-        // neutral range
-        MinMax* mm = p.mm[s] + nd.cm_off;
-        const uint32_t span = j1 - j0;
-        for (uint32_t i = threadIdx.x; i < nb * span; i += NT) {
-          const uint32_t q = i / span, j = i - q * span;
-          if (cmapf[q])
-            mm[(uint64_t)q * C + j0 + j] = j ? MinMax{~0ull, 0ull} : MinMax{mmlo[q], mmhi[q]};
-        }
-      }
-      __syncthreads();
     }
+    if (bad) flag_internal(c);
+    __syncthreads();
+    if (any_glb) {
+      MinMax* mm = p.mm[s] + nd.cm_off;
+      for (uint32_t q = threadIdx.x; q < nb; q += NT)
+        if (cmapf[q]) mm[(uint64_t)q * C + un.chunk] = MinMax{mmlo[q], mmhi[q]};
+    }
+    __syncthreads();
   }
 }
 
