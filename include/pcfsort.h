@@ -41,6 +41,17 @@
  *     pcf_workspace_bytes(...) bytes, or d_ws = NULL to let the library
  *     allocate stream-ordered memory for the call.
  *   - n and segment lengths with a uint32 payload must be < 2^32.
+ *
+ * Debugging switches (environment, read once per process):
+ *   - PCF_SYNC=1: every sort call waits for its work and returns its data
+ *     status, also when given a status word (not while `stream` is being
+ *     captured into a graph).
+ *   - PCF_TRACE=1: as PCF_SYNC, and one line per call on stderr: keys,
+ *     segments, payload, nodes/units/keys of every level that ran, LDS items
+ *     per class, status and overflow flags.
+ *   - PCF_NO_GRAPH=1: segmented calls launch eagerly instead of replaying a
+ *     captured graph.
+ *   - PCF_DEBUG=1: the call site of a failed HIP call is printed to stderr.
  */
 #ifndef PCFSORT_H
 #define PCFSORT_H

@@ -935,6 +935,54 @@ size_t workspace_for(int key_type, size_t n, int has_pay, uint32_t nseg, int int
   return make_layout(n, has_pay, nseg ? nseg : 1, cp.cover, int_keys, 0, 0).total;
 }
 
+// Debugging switches, read from the environment once:
+//   PCF_SYNC=1   every call waits for its work and returns its data status
+//                (also a call given a status word, which otherwise returns
+//                after enqueue);
+//   PCF_TRACE=1  the same, and one line per call on stderr: keys, segments,
+//                payload, nodes / units / keys of every level that ran, LDS
+//                items per class, status and overflow flags.
+// Neither applies while the caller's stream is being captured into a graph.
+struct DebugEnv {
+  bool sync, trace;
+};
+static bool env_on(const char* name) {
+  const char* v = getenv(name);
+  return v && *v && strcmp(v, "0") != 0;
+}
+static const DebugEnv& debug_env() {
+  static const DebugEnv e = {env_on("PCF_SYNC") || env_on("PCF_TRACE"), env_on("PCF_TRACE")};
+  return e;
+}
+
+// Waits for a finished call's work, prints its trace line if asked, and
+// returns its data status (PCF_OK when it has none).
+static int debug_finish(const SortArgs& a, const Layout& lay, const char* ws) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  PCF_HIP(hipStreamIsCapturing(a.stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return PCF_OK;
+  PCF_HIP(hipStreamSynchronize(a.stream));
+  Ctl hc;
+  PCF_HIP(hipMemcpy(&hc, ws + lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  int32_t st = hc.status;
+  if (st == 0 && hc.overflow) st = (hc.overflow & OVF_INTERNAL) ? PCF_ERR_HIP : PCF_ERR_OUT_OF_MEMORY;
+  if (debug_env().trace) {
+    char line[1024];
+    int o = snprintf(line, sizeof line, "pcf: %s n=%llu segments=%u payload=%d levels=[",
+                     a.key_type == PCF_KEY_F64 ? "f64" : "u64", (unsigned long long)a.n, a.nseg,
+                     a.vals_out != nullptr ? 1 : 0);
+    for (int L = 0; L < MAX_LEVELS && o < (int)sizeof line - 64; ++L) {
+      if (hc.lv[L].num_nodes == 0) break;
+      o += snprintf(line + o, sizeof line - o, "%s%u/%u/%llu", L ? " " : "", hc.lv[L].num_nodes,
+                    hc.lv[L].num_units, (unsigned long long)hc.lv[L].keys);
+    }
+    snprintf(line + o, sizeof line - o, "] items=[%u %u %u] status=%d overflow=%u\n", hc.item_count[0],
+             hc.item_count[1], hc.item_count[2], (int)hc.status, hc.overflow);
+    fputs(line, stderr);
+  }
+  return st;
+}
+
 int run_sort(const SortArgs& a) {
   if (a.key_type != PCF_KEY_F64 && a.key_type != PCF_KEY_U64) return PCF_ERR_INVALID_ARGUMENT;
   if (a.n == 0) {
@@ -974,6 +1022,7 @@ int run_sort(const SortArgs& a) {
     rc = dispatch(a, lay, ws, cp, has_pay, chain_levels(a.n, pol.lds_cap));
   else
     rc = dispatch(a, lay, ws, cp, has_pay, 0);
+  if (rc == PCF_OK && debug_env().sync) rc = debug_finish(a, lay, ws);
   if (own) {
     hipError_t e = hipFreeAsync(ws, a.stream);
     if (e != hipSuccess && rc == PCF_OK) rc = hip_fail(e);
